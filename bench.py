@@ -1,0 +1,179 @@
+"""Benchmark: ray-voxel samples/s of one forward projection plus one dose
+deposit over all angles of the full-optics workload, on one GPU.
+
+A step is one pass of the whole hot path over one synthetic target: the
+forward projection of the 256^3 target for all 360 angles, then the dose
+deposit of those projections.  Inputs are resident in HBM before the timed
+region; the geometry (ray tracing) is set up once outside it.
+
+Prints one JSON line (rank 0).  Only one GPU is used: --gpus above 1 exits
+with a message.
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Algorithmic arithmetic of one ray-voxel sample (both operators): position
+# 3 FMA (6), fractional offsets 3, trilinear weights or lerps 21, attenuation
+# argument and exp2 2, scaling and accumulation 2 = 34 FLOP.
+FLOP_PER_SAMPLE = 34
+# Gather-byte model: the 8 FP32 corner values a sample reads (or updates).
+GATHER_BYTES_PER_SAMPLE = 32
+PEAK_FP32_VECTOR_TFLOPS = 157.3
+PEAK_HBM_GBPS = 8000.0
+
+WORKLOAD_NAME = ("c2: 256^3 FP32 target, 360 angles, 256x256 DMD, thin-lens projector "
+                 "(10 deg edge chief ray), 16 pupil samples (12.2 deg), refracting vial "
+                 "R_o 120 / R_i 112, n 1/1.47/1.49, alpha 0.005/voxel, step 0.5")
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("project.hip", "vam_internal.h"):
+        h.update(open(os.path.join(ROOT, "paper_2211_03516_amd", "csrc", f), "rb").read())
+    return h.hexdigest()
+
+
+def load_traffic(kernel):
+    """HBM bytes per launch from committed rocprofv3 counter runs, or None
+    when the kernel source changed since they were taken."""
+    path = os.path.join(ROOT, "profiles", "traffic_c2.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+    except ValueError:
+        return None
+    if d.get("source_sha256") != kernel_source_hash() or kernel not in d:
+        return None
+    k = d[kernel]
+    return k.get("fetch_bytes", 0) + k.get("write_bytes", 0)
+
+
+def cpu_baseline(p, target, threads):
+    """The FP64 oracle on a bounded sample of the same workload."""
+    import numpy as np
+    import oracle
+    og = oracle.Geometry(p)
+    angles = [0, 180]
+    n_samples = 0
+    t0 = time.perf_counter()
+    P = oracle.forward(og, target, a0=0, na=1, nthreads=threads)
+    P2 = oracle.forward(og, target, a0=180, na=1, nthreads=threads)
+    oracle.adjoint(og, P, a0=0, na=1, nthreads=threads)
+    oracle.adjoint(og, P2, a0=180, na=1, nthreads=threads)
+    dt = time.perf_counter() - t0
+    for a in angles:
+        n_samples += 2 * oracle.count_samples(og, a0=a, na=1, nthreads=threads)
+    return {
+        "value": n_samples / dt, "unit": "samples/s", "cores": threads, "kind": "oracle",
+        "sample": "forward + dose deposit of angles 0 and 180 of the same workload "
+                  "(%d samples, %.1f s wall, FP64 C++ std::thread)" % (n_samples, dt),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--adjoint-variant", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-threads", type=int, default=0)
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: the projector pair is built and timed on a "
+              "single MI355X (angle-block sharding across GPUs is a design note, not run).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_2211_03516_amd as vam
+    import synth
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a HIP device", file=sys.stderr)
+        sys.exit(1)
+    dev = torch.device("cuda:0")
+    p = synth.workload("c2")
+    target, _ = synth.random_config2_target(p["nx"], p["r_inner"], seed=args.seed)
+    t_setup = time.perf_counter()
+    g = vam.Geometry(p)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t_setup
+    g.set_adjoint_variant(args.adjoint_variant)
+    rays_hit, samples_per_pass = g.stats()
+    vol = torch.from_numpy(target).to(dev)
+    proj = torch.empty(g.proj_shape, device=dev)
+    dose = torch.empty(g.vol_shape, device=dev)
+
+    def step():
+        g.forward(vol, out=proj)
+        g.back(proj, out=dose)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    fwd_ms, back_ms = [], []
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+        # kernel events are read after the timed region
+        torch.cuda.synchronize()
+        f, b = g.kernel_times()
+        fwd_ms.append(f)
+        back_ms.append(b)
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    total_ms = ev0.elapsed_time(ev1)
+    ms_per_step = total_ms / args.steps
+    value = 2.0 * samples_per_pass * args.steps / (total_ms * 1e-3)
+
+    f_avg, b_avg = float(np.mean(fwd_ms)), float(np.mean(back_ms))
+    dom, dom_ms = ("k_back", b_avg) if b_avg >= f_avg else ("k_forward", f_avg)
+    flop = FLOP_PER_SAMPLE * samples_per_pass
+    achieved = flop / (dom_ms * 1e-3) / 1e12
+    traffic = load_traffic(dom)
+    roofline = {
+        "bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
+        "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": traffic,
+        "kernel": dom, "flop_per_sample": FLOP_PER_SAMPLE, "launch_ms": dom_ms,
+    }
+    gather_gbps = GATHER_BYTES_PER_SAMPLE * samples_per_pass / (dom_ms * 1e-3) / 1e9
+    out = {
+        "metric": "ray-voxel samples/s fwd+adj", "value": value, "unit": "samples/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic (seeded union of spheres/boxes/tori, seed %d)" % args.seed,
+        "config": {"workload": WORKLOAD_NAME, "samples_per_pass": samples_per_pass,
+                   "rays_hit": rays_hit, "adjoint_variant": args.adjoint_variant},
+        "roofline": roofline,
+        "kernels_ms": {"k_forward": f_avg, "k_back": b_avg},
+        "gather_model": {"bytes_per_sample": GATHER_BYTES_PER_SAMPLE, "kernel": dom,
+                         "GBps": gather_gbps, "frac_of_hbm_peak": gather_gbps / PEAK_HBM_GBPS},
+        "setup_s": t_setup, "wall_s": wall,
+    }
+    if not args.no_cpu_baseline:
+        threads = args.cpu_threads or min(16, os.cpu_count() or 1)
+        out["cpu_baseline"] = cpu_baseline(p, target, threads)
+    g.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

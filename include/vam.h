@@ -1,0 +1,194 @@
+/*
+ * vam.h -- C ABI of libvam, the MI355X (gfx950) 3D ray-traced projector pair
+ * for tomographic volumetric additive manufacturing.
+ *
+ * Method: Webber et al., "Versatile volumetric additive manufacturing with
+ * 3D ray tracing".  Rays are cast per DMD pixel across the projector's
+ * aperture stop (Sec. 2.1), refracted by vector Snell's law at the
+ * air-glass and glass-resin vial walls and stopped at the far inner wall
+ * (Sec. 2.1), sampled with the anti-aliasing weights of Sec. 2.2
+ * ("Anti-aliasing"), and used both for the tomographic projection
+ * (Sec. 2.4) and for the dose deposit with Fresnel and Beer-Lambert
+ * transmission (Sec. 2.5), for every rotation angle.
+ *
+ * Conventions (all lengths in voxel units):
+ *   lab frame   vial axis +z through the origin, light travels +y, the
+ *               projector's focus plane is y = 0 (rotation axis at best
+ *               focus, Sec. 2.8);
+ *   volume      V[z][y][x], x fastest; voxel (i,j,k) is centred at
+ *               (i-(nx-1)/2, j-(ny-1)/2, k-(nz-1)/2) in the volume frame;
+ *   rotation    at angle theta the vial has turned by +theta about +z, so a
+ *               lab point q is at Rz(-theta) q in the volume frame;
+ *   projections P[angle][v][u], u fastest; pixel (u,v) images to
+ *               Q = ((u-(n_u-1)/2) pitch_u, 0, (v-(n_v-1)/2) pitch_v);
+ *   samples     s_k = (k+1/2) step from the resin entry, k < K =
+ *               floor(L/step + 1/2), L the resin chord; sample weight
+ *               c_k = (T1 T2 / n_pupil) step exp(-alpha s_k);
+ *   weights     trilinear tent over the 8 voxel centres around a sample;
+ *               voxels outside the grid read 0 and receive nothing.
+ *
+ * The forward operator A maps a volume to projections,
+ *   P[a][v][u] = sum_j sum_k c_k sum_corners W V,
+ * and the dose deposit is its exact transpose, D = A^T P.
+ *
+ * Memory and streams: every volume, projection and dose pointer is a DEVICE
+ * pointer owned by the caller, contiguous, 16-byte aligned, on the device
+ * that was current at vam_setup_geometry.  Calls are asynchronous and
+ * stream-ordered on the given stream; a handle may be used from one stream
+ * at a time.  No call throws; each returns a vam_status and, on failure,
+ * sets a thread-local message readable with vam_last_error().
+ */
+#ifndef VAM_H
+#define VAM_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  VAM_OK = 0,
+  VAM_ERR_INVALID_ARG = -1,   /* bad descriptor, pointer, size or range    */
+  VAM_ERR_UNSUPPORTED = -2,   /* valid request this build does not handle  */
+  VAM_ERR_OUT_OF_MEMORY = -3, /* a device allocation failed                */
+  VAM_ERR_HIP = -4,           /* a HIP runtime call or launch failed       */
+  VAM_ERR_BAD_HANDLE = -5     /* NULL or destroyed geometry handle         */
+} vam_status;
+
+/* Element type of caller buffers.  Reduced types are rounded to nearest
+ * even on store; all ray sums accumulate in FP32. */
+typedef enum { VAM_F32 = 0, VAM_BF16 = 1, VAM_F16 = 2 } vam_dtype;
+
+/* Projector models (Sec. 2.6.1 and 2.6.2). */
+typedef enum {
+  VAM_TELECENTRIC = 0, /* chief rays along +y; pupil = sin(half divergence) */
+  VAM_THIN_LENS = 1    /* ideal lens at the stop, plane y = -focus_distance;
+                          pupil = stop radius                                */
+} vam_projector;
+
+enum {
+  VAM_NO_FRESNEL = 1u  /* refract at the walls but transmit all power */
+};
+
+/* Printer and volume geometry.  Host arrays are copied at setup. */
+typedef struct {
+  int32_t nx, ny, nz;        /* volume size, each in [1, 2048]              */
+  int32_t n_u, n_v;          /* DMD pixels, each in [1, 8192]               */
+  double pitch_u, pitch_v;   /* pixel pitch on the focus plane, > 0         */
+  int32_t n_angles;          /* >= 1                                        */
+  const double* angles_rad;  /* [n_angles], or NULL for 2 pi a / n_angles   */
+  int32_t projector;         /* vam_projector                               */
+  double focus_distance;     /* thin lens: > r_outer                        */
+  double pupil;              /* see vam_projector; >= 0 (< 1 telecentric)   */
+  int32_t n_pupil;           /* rays per pixel, in [1, 1024]                */
+  const double* pupil_xy;    /* [n_pupil][2] points in the unit disk, or
+                                NULL when n_pupil == 1 (chief ray)          */
+  double r_outer, r_inner;   /* vial radii, r_outer >= r_inner > 0; equal
+                                radii mean an index-matched vial (no walls,
+                                no refraction, T = 1)                       */
+  double n_air, n_glass, n_resin; /* refractive indices, each >= 1          */
+  double alpha;              /* absorption per voxel length in resin, >= 0  */
+  double step;               /* sample spacing along the ray, > 0           */
+  uint32_t flags;            /* VAM_NO_FRESNEL                              */
+} vam_geometry_desc;
+
+typedef struct vam_geometry* vam_geometry_t;
+
+/* Trace every ray of every pixel and pupil point through the optics and the
+ * vial walls (Sec. 2.1; Fresnel factors of Sec. 2.5) in FP64 on the device
+ * and keep the resin segments as the handle's ray table.  Allocates the ray
+ * table and the padded working volumes (owned by the handle).  Synchronises
+ * `stream` before returning.  Errors: VAM_ERR_INVALID_ARG for a descriptor
+ * outside the ranges above or a NULL `out`; VAM_ERR_OUT_OF_MEMORY;
+ * VAM_ERR_HIP. */
+vam_status vam_setup_geometry(const vam_geometry_desc* desc, hipStream_t stream,
+                              vam_geometry_t* out);
+
+/* Free the handle and everything it owns.  NULL is accepted.  The caller
+ * must ensure no call using the handle is still running on the device. */
+vam_status vam_destroy_geometry(vam_geometry_t h);
+
+/* Forward projection (Sec. 2.4, with the Sec. 2.5 transmission factors):
+ * writes proj[a - angle_begin][v][u] for angles angle_begin ..
+ * angle_begin+angle_count-1 from vol[nz][ny][nx].  vol_t and proj_t select
+ * the element types.  Deterministic: the same inputs give the same bits.
+ * Errors: VAM_ERR_BAD_HANDLE; VAM_ERR_INVALID_ARG for NULL pointers, bad
+ * dtypes or an angle range outside [0, n_angles); VAM_ERR_HIP. */
+vam_status vam_forward_project(vam_geometry_t h, const void* vol, vam_dtype vol_t,
+                               void* proj, vam_dtype proj_t,
+                               int32_t angle_begin, int32_t angle_count,
+                               hipStream_t stream);
+
+/* Dose deposit (Sec. 2.5), the exact transpose of vam_forward_project over
+ * the same angle range: dose[nz][ny][nx] (FP32) receives
+ * sum_a A_a^T proj[a - angle_begin].  accumulate != 0 adds to dose,
+ * otherwise dose is overwritten.  Summation order is unspecified (results
+ * may differ in the last bits between runs).  Errors as for
+ * vam_forward_project. */
+vam_status vam_back_project(vam_geometry_t h, const void* proj, vam_dtype proj_t,
+                            float* dose, int32_t accumulate,
+                            int32_t angle_begin, int32_t angle_count,
+                            hipStream_t stream);
+
+/* One projected gradient step of the dose-threshold loss, standing in for
+ * the paper's iterative projection optimisation (Sec. 2.7), over all
+ * angles:
+ *   d = A^T g,  sig = 1/(1+exp(-sharpness (d - threshold))),
+ *   loss = mean over voxels of (sig - target)^2,
+ *   grad = A [ (2/N)(sig - target) sig (1-sig) sharpness ],
+ *   g <- g - lr grad, then g <- max(g, 0) if clamp_nonneg.
+ * target: FP32 [nz][ny][nx]; proj: FP32 [n_angles][n_v][n_u], updated in
+ * place; dose (optional, may be NULL): FP32 [nz][ny][nx] receives d; the
+ * loss is reduced in FP64.  loss_out (optional) receives the loss of the
+ * projections BEFORE the update; passing it synchronises `stream`. */
+typedef struct {
+  double threshold;     /* gelation dose threshold, e.g. 0.8 */
+  double sharpness;     /* sigmoid slope kappa, > 0          */
+  double lr;            /* step size, >= 0                   */
+  int32_t clamp_nonneg; /* 1: project onto g >= 0            */
+} vam_opt_params;
+
+vam_status vam_optimize_step(vam_geometry_t h, const float* target, float* proj,
+                             float* dose, const vam_opt_params* params,
+                             double* loss_out, hipStream_t stream);
+
+/* Ray-table statistics: rays that reach the resin, and ray-voxel samples
+ * over all angles whose anti-aliasing stencil touches the grid (one pass of
+ * vam_forward_project or vam_back_project over all angles processes this
+ * many samples).  Either pointer may be NULL. */
+vam_status vam_ray_table_stats(vam_geometry_t h, int64_t* rays_hit,
+                               int64_t* samples_per_pass);
+
+/* Copy the FP64 resin segments to host memory: for every ray in order
+ * ((j * n_v + v) * n_u + u), 12 doubles: entry point e (3), resin direction
+ * (3), chord length L, sample count K, weight T1 T2 / n_pupil, T1, T2,
+ * hit flag (1 or 0).  `out` holds n_u * n_v * n_pupil * 12 doubles.
+ * Synchronises the handle's setup stream. */
+vam_status vam_export_rays(vam_geometry_t h, double* out);
+
+/* Select the dose-deposit kernel: 0 = default (fastest measured),
+ * 1 = ray-driven scatter with direct atomics, 2 = ray-driven scatter with
+ * in-register run aggregation.  Other values: VAM_ERR_INVALID_ARG. */
+vam_status vam_set_adjoint_variant(vam_geometry_t h, int32_t variant);
+
+/* Instrumentation: device time (ms) of the main kernel of the last
+ * vam_forward_project and of the last vam_back_project on this handle,
+ * from HIP events recorded on the caller's stream right around that kernel
+ * (the small copy kernels around it are excluded).  -1 if no such call has
+ * been made.  The caller must have synchronised the stream.  Either pointer
+ * may be NULL. */
+vam_status vam_kernel_times(vam_geometry_t h, float* forward_ms, float* back_ms);
+
+/* Thread-local description of the last failure on this thread ("" if
+ * none).  The string stays valid until the next vam_* call on the thread. */
+const char* vam_last_error(void);
+
+/* Library version, major * 10000 + minor * 100 + patch. */
+int32_t vam_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* VAM_H */

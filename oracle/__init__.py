@@ -83,6 +83,16 @@ def _dptr(a):
     return a.ctypes.data_as(_D)
 
 
+def default_threads():
+    """Worker threads for the oracle: the host's cores, at most 16 (the CPU
+    share of one GPU on a shared box)."""
+    return max(1, min(16, os.cpu_count() or 1))
+
+
+def _nt(n):
+    return n if n and n > 0 else default_threads()
+
+
 class Geometry:
     """Oracle geometry built from a workload parameter dict (synth.configs).
     Keeps the numpy arrays the struct points into alive."""
@@ -119,7 +129,7 @@ def trace(geom, nthreads=0):
     """All ray records, shape (nv, nu, n_pupil, R_SIZE)."""
     p = geom.p
     out = np.zeros((p["nv"], p["nu"], p["n_pupil"], R_SIZE))
-    lib().oracle_trace(geom.ref, _dptr(out), nthreads)
+    lib().oracle_trace(geom.ref, _dptr(out), _nt(nthreads))
     return out
 
 
@@ -136,7 +146,7 @@ def forward(geom, vol, a0=0, na=None, nthreads=0):
     v = np.ascontiguousarray(vol, dtype=np.float64)
     assert v.shape == geom.vol_shape
     out = np.zeros((na, p["nv"], p["nu"]))
-    lib().oracle_forward(geom.ref, _dptr(v), a0, na, _dptr(out), nthreads)
+    lib().oracle_forward(geom.ref, _dptr(v), a0, na, _dptr(out), _nt(nthreads))
     return out
 
 
@@ -148,7 +158,7 @@ def forward_pixels(geom, vol, ang, vv, uu, nthreads=0):
     out = np.zeros(len(ang))
     lib().oracle_forward_pixels(geom.ref, _dptr(v), len(ang),
                                 ang.ctypes.data_as(_I32), vv.ctypes.data_as(_I32),
-                                uu.ctypes.data_as(_I32), _dptr(out), nthreads)
+                                uu.ctypes.data_as(_I32), _dptr(out), _nt(nthreads))
     return out
 
 
@@ -159,13 +169,13 @@ def adjoint(geom, proj, a0=0, na=None, nthreads=0):
     na = pr.shape[0] if na is None else na
     assert pr.shape == (na, p["nv"], p["nu"])
     out = np.zeros(geom.vol_shape)
-    lib().oracle_adjoint(geom.ref, _dptr(pr), a0, na, _dptr(out), nthreads)
+    lib().oracle_adjoint(geom.ref, _dptr(pr), a0, na, _dptr(out), _nt(nthreads))
     return out
 
 
 def count_samples(geom, a0=0, na=None, nthreads=0):
     na = geom.p["n_angles"] - a0 if na is None else na
-    return int(lib().oracle_count_samples(geom.ref, a0, na, nthreads))
+    return int(lib().oracle_count_samples(geom.ref, a0, na, _nt(nthreads)))
 
 
 def loss_grad(geom, target, proj, kappa, thr, nthreads=0):
@@ -176,7 +186,7 @@ def loss_grad(geom, target, proj, kappa, thr, nthreads=0):
     dose = np.zeros(geom.vol_shape)
     grad = np.zeros((p["n_angles"], p["nv"], p["nu"]))
     loss = lib().oracle_loss_grad(geom.ref, _dptr(t), _dptr(pr), kappa, thr,
-                                  _dptr(dose), _dptr(grad), nthreads)
+                                  _dptr(dose), _dptr(grad), _nt(nthreads))
     return loss, dose, grad
 
 

@@ -1,0 +1,434 @@
+// The projector pair on gfx950: forward projection (Sec. 2.4 of Webber et
+// al., with the transmission factors of Sec. 2.5) and its exact transpose,
+// the dose deposit (Sec. 2.5).
+//
+// Work decomposition.  One lane per DMD pixel and angle; the lane marches
+// the n_pupil rays of its pixel one after the other (finite etendue,
+// Sec. 2.4/2.5) and sums them in registers, so the pupil reduction needs no
+// cross-lane traffic and a wave writes 64 consecutive projection values of
+// one row (coalesced).  Lanes of a wave are 64 neighbouring pixels of one
+// row: at a given step their samples sit side by side in the volume, which
+// keeps the gathers of a wave within a few cache lines.
+//
+// Sampling.  The ray table keeps each resin segment as its midpoint and
+// direction (lab frame).  Per angle the midpoint and direction are rotated
+// into the volume frame in FP64 and rounded once; sample k is then at
+// g = m + t_k d with t_k = (k + 1/2 - K/2) step, one FMA per axis, short
+// lever arms and no accumulated drift.  The attenuation factor is
+// exp2(-alpha log2(e) t_k) times a per-ray constant that carries
+// exp(-alpha K step / 2), so every sample costs one exp2.  Anti-aliasing
+// weights (Sec. 2.2) are the trilinear tent over the 8 surrounding voxel
+// centres.
+//
+// Bounds.  The working volumes carry two zero voxels of padding per side.
+// Per ray and angle the sample range is clipped to padded coordinates
+// [0.5, n + 2.5] (the stencil touches the grid only in (1, n + 2)), and every
+// position is also clamped into [0, n + 2.5] before indexing, so all eight
+// corners stay inside the padded array whatever the rounding.
+
+#include <cmath>
+
+#include "vam_internal.h"
+
+namespace vam {
+
+struct MarchParams {
+  const RayRec* rays;
+  const double2* cs;   // (cos, sin) per angle
+  int nu, nv, np;
+  int a0;
+  int sx;              // padded x stride
+  int sxy;             // padded slice stride
+  double cx, cy;       // centre offsets into padded x, y
+  float hix, hiy;      // clip upper bounds: n + 2.5
+  float clx, cly, clz; // clamp upper bounds: n + 2.5
+  float step;
+  float nb;            // -alpha log2(e)
+};
+
+// --------------------------------------------------------- element access --
+
+__device__ inline float load_elem(const float* p, int64_t i) { return p[i]; }
+__device__ inline float load_elem(const uint16_t* p, int64_t i) {
+  return __uint_as_float((uint32_t)p[i] << 16);
+}
+__device__ inline float load_elem(const __half* p, int64_t i) { return __half2float(p[i]); }
+
+__device__ inline void store_elem(float* p, int64_t i, float x) { p[i] = x; }
+__device__ inline void store_elem(uint16_t* p, int64_t i, float x) {
+  uint32_t u = __float_as_uint(x);
+  uint16_t b;
+  if ((u & 0x7fffffffu) > 0x7f800000u) {
+    b = (uint16_t)((u >> 16) | 0x40u);  // quiet NaN
+  } else {
+    u += 0x7fffu + ((u >> 16) & 1u);   // round to nearest even
+    b = (uint16_t)(u >> 16);
+  }
+  p[i] = b;
+}
+__device__ inline void store_elem(__half* p, int64_t i, float x) { p[i] = __float2half_rn(x); }
+
+// ------------------------------------------------------- per-ray set-up ----
+
+struct Seg {
+  float gx, gy, gz;   // midpoint, padded grid coordinates (volume frame)
+  float dx, dy, dz;   // direction (volume frame)
+  float t0;           // t of sample k0 of the z-clipped range
+  float cw;
+  int k0, k1;         // samples [k0, k1) relative to t0
+};
+
+__device__ inline void clip_axis(float g, float d, float lo, float hi, float& tlo, float& thi) {
+  if (fabsf(d) > 1e-20f) {
+    float inv = 1.0f / d;
+    float ta = (lo - g) * inv, tb = (hi - g) * inv;
+    tlo = fmaxf(tlo, fminf(ta, tb));
+    thi = fminf(thi, fmaxf(ta, tb));
+  } else if (!(g >= lo && g <= hi)) {
+    thi = -INFINITY;
+  }
+}
+
+// Rotate ray r into the volume frame of angle (c, s) and clip its sample
+// range to the padded grid.  Returns false when nothing is left.
+__device__ inline bool segment(const MarchParams& P, const RayRec& R, double c, double s, Seg& g) {
+  if (R.n <= 0) return false;
+  g.gx = (float)(c * R.mx + s * R.my + P.cx);
+  g.gy = (float)(-s * R.mx + c * R.my + P.cy);
+  g.gz = R.gz;
+  g.dx = (float)(c * R.dx + s * R.dy);
+  g.dy = (float)(-s * R.dx + c * R.dy);
+  g.dz = R.dz;
+  g.t0 = R.t0;
+  g.cw = R.cw;
+  float tlo = R.t0;
+  float thi = R.t0 + (float)(R.n - 1) * P.step;
+  clip_axis(g.gx, g.dx, 0.5f, P.hix, tlo, thi);
+  clip_axis(g.gy, g.dy, 0.5f, P.hiy, tlo, thi);
+  if (!(thi >= tlo)) return false;
+  // one spare sample on each side is harmless: it reads or writes padding
+  int k0 = (int)floorf((tlo - R.t0) / P.step);
+  int k1 = (int)ceilf((thi - R.t0) / P.step) + 1;
+  g.k0 = max(k0, 0);
+  g.k1 = min(k1, R.n);
+  return g.k1 > g.k0;
+}
+
+// Position of a sample, clamped into the padded array, its base voxel index
+// and fractional offsets.
+__device__ inline int cell(const MarchParams& P, const Seg& g, float t, float& fx, float& fy,
+                           float& fz) {
+  float x = __builtin_amdgcn_fmed3f(fmaf(t, g.dx, g.gx), 0.0f, P.clx);
+  float y = __builtin_amdgcn_fmed3f(fmaf(t, g.dy, g.gy), 0.0f, P.cly);
+  float z = __builtin_amdgcn_fmed3f(fmaf(t, g.dz, g.gz), 0.0f, P.clz);
+  float ix = floorf(x), iy = floorf(y), iz = floorf(z);
+  fx = x - ix;
+  fy = y - iy;
+  fz = z - iz;
+  return ((int)iz * P.sxy + (int)iy * P.sx) + (int)ix;
+}
+
+// ---------------------------------------------------------------- kernels --
+
+// Forward projection, one lane per (pixel, angle).  Block (64, 4): 64 pixels
+// of 4 consecutive rows; grid (ceil(nu/64), ceil(nv/4), angles).
+template <typename PT>
+__global__ __launch_bounds__(256) void k_forward(MarchParams P, const float* __restrict__ vol,
+                                                 PT* __restrict__ proj) {
+  const int u = blockIdx.x * 64 + threadIdx.x;
+  const int v = blockIdx.y * 4 + threadIdx.y;
+  const int a = blockIdx.z;
+  if (u >= P.nu || v >= P.nv) return;
+  const double2 cs = P.cs[P.a0 + a];
+  const int64_t plane = (int64_t)P.nv * P.nu;
+  float acc = 0.0f;
+  for (int j = 0; j < P.np; ++j) {
+    const RayRec R = P.rays[j * plane + (int64_t)v * P.nu + u];
+    Seg g;
+    if (!segment(P, R, cs.x, cs.y, g)) continue;
+    float sum = 0.0f;
+    float kf = (float)g.k0;
+    for (int k = g.k0; k < g.k1; ++k, kf += 1.0f) {
+      const float t = fmaf(kf, P.step, g.t0);
+      float fx, fy, fz;
+      const float* p = vol + cell(P, g, t, fx, fy, fz);
+      const float v000 = p[0], v001 = p[1];
+      const float v010 = p[P.sx], v011 = p[P.sx + 1];
+      const float v100 = p[P.sxy], v101 = p[P.sxy + 1];
+      const float v110 = p[P.sxy + P.sx], v111 = p[P.sxy + P.sx + 1];
+      const float c00 = fmaf(fx, v001 - v000, v000);
+      const float c01 = fmaf(fx, v011 - v010, v010);
+      const float c10 = fmaf(fx, v101 - v100, v100);
+      const float c11 = fmaf(fx, v111 - v110, v110);
+      const float c0 = fmaf(fy, c01 - c00, c00);
+      const float c1 = fmaf(fy, c11 - c10, c10);
+      const float val = fmaf(fz, c1 - c0, c0);
+      sum = fmaf(exp2f(P.nb * t), val, sum);
+    }
+    acc = fmaf(g.cw, sum, acc);
+  }
+  store_elem(proj, ((int64_t)a * P.nv + v) * P.nu + u, acc);
+}
+
+// Dose deposit, the transpose of k_forward: the same lanes, the same
+// samples and weights, scattered with hardware FP32 atomics into the padded
+// accumulator.  AGG = true keeps the 8 corner sums of the current cell in
+// registers while consecutive samples of a ray stay in one cell and flushes
+// them when the cell changes.
+template <typename PT, bool AGG>
+__global__ __launch_bounds__(256) void k_back(MarchParams P, const PT* __restrict__ proj,
+                                              float* __restrict__ dose) {
+  const int u = blockIdx.x * 64 + threadIdx.x;
+  const int v = blockIdx.y * 4 + threadIdx.y;
+  const int a = blockIdx.z;
+  if (u >= P.nu || v >= P.nv) return;
+  const float pv = load_elem(proj, ((int64_t)a * P.nv + v) * P.nu + u);
+  if (pv == 0.0f) return;
+  const double2 cs = P.cs[P.a0 + a];
+  const int64_t plane = (int64_t)P.nv * P.nu;
+  for (int j = 0; j < P.np; ++j) {
+    const RayRec R = P.rays[j * plane + (int64_t)v * P.nu + u];
+    Seg g;
+    if (!segment(P, R, cs.x, cs.y, g)) continue;
+    const float scale = g.cw * pv;
+    float kf = (float)g.k0;
+    int cur = -1;
+    float w[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int k = g.k0; k < g.k1; ++k, kf += 1.0f) {
+      const float t = fmaf(kf, P.step, g.t0);
+      float fx, fy, fz;
+      const int i = cell(P, g, t, fx, fy, fz);
+      const float e = scale * exp2f(P.nb * t);
+      const float z1 = e * fz, z0 = e - z1;
+      const float y01 = z0 * fy, y00 = z0 - y01;
+      const float y11 = z1 * fy, y10 = z1 - y11;
+      const float q[8] = {y00 - y00 * fx, y00 * fx, y01 - y01 * fx, y01 * fx,
+                          y10 - y10 * fx, y10 * fx, y11 - y11 * fx, y11 * fx};
+      if (AGG) {
+        if (i != cur) {
+          if (cur >= 0) {
+            float* d = dose + cur;
+            unsafeAtomicAdd(d, w[0]);
+            unsafeAtomicAdd(d + 1, w[1]);
+            unsafeAtomicAdd(d + P.sx, w[2]);
+            unsafeAtomicAdd(d + P.sx + 1, w[3]);
+            unsafeAtomicAdd(d + P.sxy, w[4]);
+            unsafeAtomicAdd(d + P.sxy + 1, w[5]);
+            unsafeAtomicAdd(d + P.sxy + P.sx, w[6]);
+            unsafeAtomicAdd(d + P.sxy + P.sx + 1, w[7]);
+          }
+          cur = i;
+#pragma unroll
+          for (int c = 0; c < 8; ++c) w[c] = q[c];
+        } else {
+#pragma unroll
+          for (int c = 0; c < 8; ++c) w[c] += q[c];
+        }
+      } else {
+        float* d = dose + i;
+        unsafeAtomicAdd(d, q[0]);
+        unsafeAtomicAdd(d + 1, q[1]);
+        unsafeAtomicAdd(d + P.sx, q[2]);
+        unsafeAtomicAdd(d + P.sx + 1, q[3]);
+        unsafeAtomicAdd(d + P.sxy, q[4]);
+        unsafeAtomicAdd(d + P.sxy + 1, q[5]);
+        unsafeAtomicAdd(d + P.sxy + P.sx, q[6]);
+        unsafeAtomicAdd(d + P.sxy + P.sx + 1, q[7]);
+      }
+    }
+    if (AGG && cur >= 0) {
+      float* d = dose + cur;
+      unsafeAtomicAdd(d, w[0]);
+      unsafeAtomicAdd(d + 1, w[1]);
+      unsafeAtomicAdd(d + P.sx, w[2]);
+      unsafeAtomicAdd(d + P.sx + 1, w[3]);
+      unsafeAtomicAdd(d + P.sxy, w[4]);
+      unsafeAtomicAdd(d + P.sxy + 1, w[5]);
+      unsafeAtomicAdd(d + P.sxy + P.sx, w[6]);
+      unsafeAtomicAdd(d + P.sxy + P.sx + 1, w[7]);
+    }
+  }
+}
+
+// Caller volume -> interior of the padded FP32 working volume.
+template <typename VT>
+__global__ void k_pad(const VT* __restrict__ vol, float* __restrict__ vp, int nx, int ny, int nz,
+                      int px, int py) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t n = (int64_t)nx * ny * nz;
+  if (i >= n) return;
+  const int x = (int)(i % nx);
+  const int y = (int)((i / nx) % ny);
+  const int z = (int)(i / ((int64_t)nx * ny));
+  vp[((int64_t)(z + kPad) * py + (y + kPad)) * px + (x + kPad)] = load_elem(vol, i);
+}
+
+// Interior of the padded accumulator -> caller dose (overwrite or add).
+__global__ void k_unpad(const float* __restrict__ dp, float* __restrict__ dose, int accumulate,
+                        int nx, int ny, int nz, int px, int py) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t n = (int64_t)nx * ny * nz;
+  if (i >= n) return;
+  const int x = (int)(i % nx);
+  const int y = (int)((i / nx) % ny);
+  const int z = (int)(i / ((int64_t)nx * ny));
+  const float d = dp[((int64_t)(z + kPad) * py + (y + kPad)) * px + (x + kPad)];
+  dose[i] = accumulate ? dose[i] + d : d;
+}
+
+__global__ void k_fill(float* __restrict__ p, int64_t n, float value) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = value;
+}
+
+static MarchParams march_params(const vam_geometry* h, int a0) {
+  const vam_geometry_desc& D = h->desc;
+  MarchParams P;
+  P.rays = h->rays;
+  P.cs = h->angle_cs;
+  P.nu = D.n_u;
+  P.nv = D.n_v;
+  P.np = D.n_pupil;
+  P.a0 = a0;
+  P.sx = h->px;
+  P.sxy = h->px * h->py;
+  P.cx = 0.5 * (D.nx - 1) + kPad;
+  P.cy = 0.5 * (D.ny - 1) + kPad;
+  P.hix = (float)D.nx + 2.5f;
+  P.hiy = (float)D.ny + 2.5f;
+  P.clx = (float)D.nx + 2.5f;
+  P.cly = (float)D.ny + 2.5f;
+  P.clz = (float)D.nz + 2.5f;
+  P.step = (float)D.step;
+  P.nb = (float)(-D.alpha / std::log(2.0));
+  return P;
+}
+
+static inline unsigned blocks_for(int64_t n, int threads) { return (unsigned)((n + threads - 1) / threads); }
+
+vam_status launch_forward(vam_geometry* h, const void* vol, vam_dtype vol_t, void* proj,
+                          vam_dtype proj_t, int a0, int na, hipStream_t s) {
+  const vam_geometry_desc& D = h->desc;
+  const int64_t nvox = (int64_t)D.nx * D.ny * D.nz;
+  const unsigned vb = blocks_for(nvox, 256);
+  switch (vol_t) {
+    case VAM_F32:
+      hipLaunchKernelGGL(k_pad<float>, dim3(vb), dim3(256), 0, s, (const float*)vol, h->vol_pad,
+                         D.nx, D.ny, D.nz, h->px, h->py);
+      break;
+    case VAM_BF16:
+      hipLaunchKernelGGL(k_pad<uint16_t>, dim3(vb), dim3(256), 0, s, (const uint16_t*)vol, h->vol_pad,
+                         D.nx, D.ny, D.nz, h->px, h->py);
+      break;
+    case VAM_F16:
+      hipLaunchKernelGGL(k_pad<__half>, dim3(vb), dim3(256), 0, s, (const __half*)vol, h->vol_pad,
+                         D.nx, D.ny, D.nz, h->px, h->py);
+      break;
+  }
+  VAM_HIP_TRY(hipGetLastError(), "launching the volume copy");
+  MarchParams P = march_params(h, a0);
+  dim3 grid((D.n_u + 63) / 64, (D.n_v + 3) / 4, na), block(64, 4);
+  VAM_HIP_TRY(hipEventRecord(h->ev[0], s), "recording an event");
+  switch (proj_t) {
+    case VAM_F32:
+      hipLaunchKernelGGL(k_forward<float>, grid, block, 0, s, P, h->vol_pad, (float*)proj);
+      break;
+    case VAM_BF16:
+      hipLaunchKernelGGL(k_forward<uint16_t>, grid, block, 0, s, P, h->vol_pad, (uint16_t*)proj);
+      break;
+    case VAM_F16:
+      hipLaunchKernelGGL(k_forward<__half>, grid, block, 0, s, P, h->vol_pad, (__half*)proj);
+      break;
+  }
+  VAM_HIP_TRY(hipGetLastError(), "launching the forward projector");
+  VAM_HIP_TRY(hipEventRecord(h->ev[1], s), "recording an event");
+  h->ev_valid[0] = 1;
+  return VAM_OK;
+}
+
+template <typename PT>
+static void launch_back_t(vam_geometry* h, const PT* proj, const MarchParams& P, dim3 grid, dim3 block,
+                          hipStream_t s) {
+  if (h->adjoint_variant == 1)
+    hipLaunchKernelGGL((k_back<PT, false>), grid, block, 0, s, P, proj, h->dose_pad);
+  else
+    hipLaunchKernelGGL((k_back<PT, true>), grid, block, 0, s, P, proj, h->dose_pad);
+}
+
+vam_status launch_back(vam_geometry* h, const void* proj, vam_dtype proj_t, float* dose, int accumulate,
+                       int a0, int na, hipStream_t s) {
+  const vam_geometry_desc& D = h->desc;
+  hipLaunchKernelGGL(k_fill, dim3(blocks_for(h->pad_voxels, 256)), dim3(256), 0, s, h->dose_pad,
+                     h->pad_voxels, 0.0f);
+  VAM_HIP_TRY(hipGetLastError(), "launching the accumulator clear");
+  MarchParams P = march_params(h, a0);
+  dim3 grid((D.n_u + 63) / 64, (D.n_v + 3) / 4, na), block(64, 4);
+  VAM_HIP_TRY(hipEventRecord(h->ev[2], s), "recording an event");
+  switch (proj_t) {
+    case VAM_F32: launch_back_t(h, (const float*)proj, P, grid, block, s); break;
+    case VAM_BF16: launch_back_t(h, (const uint16_t*)proj, P, grid, block, s); break;
+    case VAM_F16: launch_back_t(h, (const __half*)proj, P, grid, block, s); break;
+  }
+  VAM_HIP_TRY(hipGetLastError(), "launching the dose deposit");
+  VAM_HIP_TRY(hipEventRecord(h->ev[3], s), "recording an event");
+  h->ev_valid[1] = 1;
+  const int64_t nvox = (int64_t)D.nx * D.ny * D.nz;
+  hipLaunchKernelGGL(k_unpad, dim3(blocks_for(nvox, 256)), dim3(256), 0, s, h->dose_pad, dose, accumulate,
+                     D.nx, D.ny, D.nz, h->px, h->py);
+  VAM_HIP_TRY(hipGetLastError(), "launching the dose copy");
+  return VAM_OK;
+}
+
+static vam_status check_common(vam_geometry* h, const void* a, const void* b, int dt, int a0, int na) {
+  if (!valid_handle(h)) return fail(VAM_ERR_BAD_HANDLE, "not a live geometry handle");
+  if (!a || !b) return fail(VAM_ERR_INVALID_ARG, "NULL buffer");
+  if (dt != VAM_F32 && dt != VAM_BF16 && dt != VAM_F16) return fail(VAM_ERR_INVALID_ARG, "unknown dtype %d", dt);
+  if (na < 1 || a0 < 0 || (int64_t)a0 + na > h->desc.n_angles)
+    return fail(VAM_ERR_INVALID_ARG, "angle range [%d, %d) outside [0, %d)", a0, a0 + na, h->desc.n_angles);
+  return VAM_OK;
+}
+
+}  // namespace vam
+
+using namespace vam;
+
+extern "C" {
+
+vam_status vam_forward_project(vam_geometry_t h, const void* vol, vam_dtype vol_t, void* proj,
+                               vam_dtype proj_t, int32_t angle_begin, int32_t angle_count,
+                               hipStream_t stream) {
+  clear_error();
+  vam_status st = check_common(h, vol, proj, vol_t, angle_begin, angle_count);
+  if (st != VAM_OK) return st;
+  if (proj_t != VAM_F32 && proj_t != VAM_BF16 && proj_t != VAM_F16)
+    return fail(VAM_ERR_INVALID_ARG, "unknown projection dtype %d", (int)proj_t);
+  VAM_HIP_TRY(hipSetDevice(h->device), "hipSetDevice");
+  return launch_forward(h, vol, vol_t, proj, proj_t, angle_begin, angle_count, stream);
+}
+
+vam_status vam_back_project(vam_geometry_t h, const void* proj, vam_dtype proj_t, float* dose,
+                            int32_t accumulate, int32_t angle_begin, int32_t angle_count,
+                            hipStream_t stream) {
+  clear_error();
+  vam_status st = check_common(h, proj, dose, proj_t, angle_begin, angle_count);
+  if (st != VAM_OK) return st;
+  VAM_HIP_TRY(hipSetDevice(h->device), "hipSetDevice");
+  return launch_back(h, proj, proj_t, dose, accumulate, angle_begin, angle_count, stream);
+}
+
+vam_status vam_kernel_times(vam_geometry_t h, float* forward_ms, float* back_ms) {
+  clear_error();
+  if (!valid_handle(h)) return fail(VAM_ERR_BAD_HANDLE, "not a live geometry handle");
+  VAM_HIP_TRY(hipSetDevice(h->device), "hipSetDevice");
+  if (forward_ms) {
+    *forward_ms = -1.0f;
+    if (h->ev_valid[0]) VAM_HIP_TRY(hipEventElapsedTime(forward_ms, h->ev[0], h->ev[1]), "reading events");
+  }
+  if (back_ms) {
+    *back_ms = -1.0f;
+    if (h->ev_valid[1]) VAM_HIP_TRY(hipEventElapsedTime(back_ms, h->ev[2], h->ev[3]), "reading events");
+  }
+  return VAM_OK;
+}
+
+}  // extern "C"

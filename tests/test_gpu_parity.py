@@ -1,0 +1,312 @@
+"""Parity of the HIP projector pair with the FP64 oracle, through the C ABI.
+
+Tolerances.  FP32 results: relative L2 error <= 1e-5 against the FP64 oracle
+on the same seeded inputs.  Reduced-precision storage: one rounding of the
+stored volume and one of the stored projection, so rel-L2 <= 2 u with
+u = 2^-8 (BF16) or 2^-11 (FP16); binary targets are exact in both.
+Ray-table fields are FP64 on both sides and must agree to 1e-12.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from synth.configs import scaled
+
+torch = pytest.importorskip("torch")
+import paper_2211_03516_amd as vam
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def relL2(x, ref):
+    x = np.asarray(x, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    return float(np.linalg.norm(x - ref) / max(np.linalg.norm(ref), 1e-300))
+
+
+def c2_small(n=64, n_pupil=16, n_angles=24, **kw):
+    """c2 optics scaled to n^3: thin lens, 10 deg edge chief ray, 12.2 deg
+    divergence, refracting vial."""
+    F = (n / 2) / math.tan(math.radians(10))
+    p = scaled(synth.workload("c2"), nx=n, ny=n, nz=n, nu=n, nv=n, focus=F,
+               pupil=F * math.tan(math.radians(6.1)), n_pupil=n_pupil,
+               r_outer=0.47 * n, r_inner=0.44 * n, alpha=0.02, n_angles=n_angles)
+    p.update(kw)
+    return p
+
+
+def gpu_geom(p):
+    say("setup geometry", {k: p[k] for k in ("nx", "ny", "nz", "nu", "nv", "n_pupil", "n_angles", "projector")})
+    g = vam.Geometry(p)
+    torch.cuda.synchronize()
+    return g
+
+
+def to_dev(a, dtype=torch.float32):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV, dtype=dtype)
+
+
+# ------------------------------------------------------------- ray table --
+
+@pytest.mark.parametrize("name", ["c1", "c2small", "c2"])
+def test_ray_table_matches_oracle_trace(name):
+    p = synth.workload("c1") if name == "c1" else (c2_small() if name == "c2small" else synth.workload("c2"))
+    g = gpu_geom(p)
+    R = g.export_rays()                        # (np, nv, nu, 12)
+    O = oracle.trace(oracle.Geometry(p))       # (nv, nu, np, 26)
+    O = np.transpose(O, (2, 0, 1, 3))
+    hit = O[..., oracle.R_HIT] == 1
+    np.testing.assert_array_equal(R[..., 11] == 1, hit)
+    say(name, "rays hit", int(hit.sum()), "of", hit.size)
+    np.testing.assert_allclose(R[hit][:, 0:3], O[hit][:, oracle.R_E:oracle.R_E + 3], rtol=0, atol=1e-12)
+    np.testing.assert_allclose(R[hit][:, 3:6], O[hit][:, oracle.R_DR:oracle.R_DR + 3], rtol=0, atol=1e-13)
+    np.testing.assert_allclose(R[hit][:, 6], O[hit][:, oracle.R_L], rtol=1e-12, atol=1e-11)
+    np.testing.assert_array_equal(R[hit][:, 7], O[hit][:, oracle.R_K])
+    np.testing.assert_allclose(R[hit][:, 8], O[hit][:, oracle.R_W], rtol=1e-13, atol=0)
+    rays_hit, samples = g.stats()
+    assert rays_hit == int(hit.sum())
+    if name != "c2":
+        assert samples == oracle.count_samples(oracle.Geometry(p))
+    g.close()
+
+
+# ----------------------------------------------------------- small parity --
+
+def _parity_case(p, vol, proj_in, tol=1e-5):
+    og = oracle.Geometry(p)
+    g = gpu_geom(p)
+    say("forward parity", p["nx"], p["n_angles"])
+    Pg = g.forward(to_dev(vol)).cpu().numpy()
+    Po = oracle.forward(og, vol)
+    e_f = relL2(Pg, Po)
+    say("adjoint parity", p["nx"], p["n_angles"])
+    Dg = g.back(to_dev(proj_in)).cpu().numpy()
+    Do = oracle.adjoint(og, proj_in)
+    e_a = relL2(Dg, Do)
+    say("rel-L2 forward %.3e adjoint %.3e" % (e_f, e_a))
+    assert np.isfinite(Pg).all() and np.isfinite(Dg).all()
+    assert e_f <= tol and e_a <= tol
+    return g, og, Pg, Po
+
+
+def test_c1_full_forward_and_adjoint():
+    p = synth.workload("c1")
+    t, _ = synth.random_config1_target(64, 32.0, seed=0)
+    Po = oracle.forward(oracle.Geometry(p), t)
+    g, og, Pg, _ = _parity_case(p, t, Po)
+    # seeded U[0,1) inputs too
+    rng = synth.SplitMix64(1)
+    x = rng.uniform(64 ** 3).reshape(64, 64, 64)
+    y = rng.uniform(90 * 64 * 64).reshape(90, 64, 64)
+    assert relL2(g.forward(to_dev(x)).cpu().numpy(), oracle.forward(og, x)) <= 1e-5
+    assert relL2(g.back(to_dev(y)).cpu().numpy(), oracle.adjoint(og, y)) <= 1e-5
+    g.close()
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_c2_optics_64(seed):
+    p = c2_small()
+    t, _ = synth.random_config2_target(64, p["r_inner"], seed=seed)
+    rng = synth.SplitMix64(100 + seed)
+    y = rng.uniform(p["n_angles"] * 64 * 64).reshape(p["n_angles"], 64, 64)
+    g, *_ = _parity_case(p, t, y)
+    g.close()
+
+
+def test_ragged_sizes_and_telecentric_pupil():
+    # sizes that are not multiples of the 64 x 4 lane tile, odd everything
+    p = scaled(synth.workload("c3"), nx=37, ny=41, nz=29, nu=70, nv=5, n_angles=7,
+               r_outer=18.0, r_inner=16.5, n_pupil=3, pitch_u=0.6, pitch_v=1.3)
+    rng = synth.SplitMix64(7)
+    x = rng.uniform(29 * 41 * 37).reshape(29, 41, 37)
+    y = rng.uniform(7 * 5 * 70).reshape(7, 5, 70)
+    g, *_ = _parity_case(p, x, y)
+    g.close()
+
+
+def test_chief_ray_only_null_pupil_and_no_fresnel():
+    p = c2_small(32, n_pupil=1, n_angles=5, flags=vam.VAM_NO_FRESNEL)
+    p["pupil_xy"] = None
+    po = dict(p, pupil_xy=np.zeros((1, 2)))
+    rng = synth.SplitMix64(8)
+    x = rng.uniform(32 ** 3).reshape(32, 32, 32)
+    g = gpu_geom(p)
+    Pg = g.forward(to_dev(x)).cpu().numpy()
+    assert relL2(Pg, oracle.forward(oracle.Geometry(po), x)) <= 1e-5
+    g.close()
+
+
+def test_rays_missing_the_vial():
+    # most pixel columns lie beside a thin vial: those rays carry nothing
+    p = scaled(synth.workload("c1"), nx=16, ny=16, nz=16, nu=16, nv=4,
+               r_outer=3.0, r_inner=3.0, n_angles=3)
+    g = gpu_geom(p)
+    hits, samples = g.stats()
+    assert 0 < hits < 16 * 4
+    x = torch.ones((16, 16, 16), device=DEV)
+    P = g.forward(x).cpu().numpy()
+    Po = oracle.forward(oracle.Geometry(p), np.ones((16, 16, 16)))
+    assert np.isfinite(P).all()
+    assert relL2(P, Po) <= 1e-5
+    assert (P[:, :, :5] == 0).all() and (P[:, :, -5:] == 0).all()
+    g.close()
+    # a vial narrower than half a pixel: every ray misses
+    p2 = dict(p, r_outer=0.2, r_inner=0.2, nu=2, nv=2)
+    g2 = gpu_geom(p2)
+    assert g2.stats() == (0, 0)
+    assert np.abs(g2.forward(x).cpu().numpy()).max() == 0
+    d = g2.back(torch.ones((3, 2, 2), device=DEV)).cpu().numpy()
+    assert np.abs(d).max() == 0
+    g2.close()
+
+
+# ---------------------------------------------------- API behaviour -------
+
+def test_angle_ranges_determinism_accumulate():
+    p = c2_small(32, n_pupil=4, n_angles=10)
+    g = gpu_geom(p)
+    rng = synth.SplitMix64(9)
+    x = to_dev(rng.uniform(32 ** 3).reshape(32, 32, 32))
+    full = g.forward(x)
+    part = g.forward(x, angle_begin=3, angle_count=5)
+    assert torch.equal(full[3:8], part)
+    again = g.forward(x)
+    assert torch.equal(full, again)            # deterministic forward
+    y = to_dev(rng.uniform(10 * 32 * 32).reshape(10, 32, 32))
+    d_all = g.back(y).double()
+    d_a = g.back(y[:4], angle_begin=0)
+    g.back(y[4:], out=d_a, accumulate=True, angle_begin=4)
+    assert relL2(d_a.double().cpu().numpy(), d_all.cpu().numpy()) <= 1e-6
+    # out-of-range angle windows are rejected
+    with pytest.raises(vam.VamError):
+        g.forward(x, angle_begin=8, angle_count=5)
+    with pytest.raises(vam.VamError):
+        g.back(y[:3], angle_begin=9)
+    g.close()
+
+
+def test_adjoint_variants_agree():
+    p = c2_small(48, n_pupil=4, n_angles=12)
+    g = gpu_geom(p)
+    rng = synth.SplitMix64(10)
+    y = to_dev(rng.uniform(12 * 48 * 48).reshape(12, 48, 48))
+    ref = oracle.adjoint(oracle.Geometry(p), y.cpu().numpy().astype(np.float64))
+    for variant in (vam.ADJ_SCATTER_DIRECT, vam.ADJ_SCATTER_AGGREGATED, vam.ADJ_DEFAULT):
+        g.set_adjoint_variant(variant)
+        say("adjoint variant", variant)
+        assert relL2(g.back(y).cpu().numpy(), ref) <= 1e-5
+    g.close()
+
+
+@pytest.mark.parametrize("dt,bound", [("bf16", 2 * 2.0 ** -8), ("f16", 2 * 2.0 ** -11)])
+def test_reduced_precision_storage(dt, bound):
+    tdt = torch.bfloat16 if dt == "bf16" else torch.float16
+    p = c2_small(64, n_pupil=8, n_angles=16)
+    t, _ = synth.random_config2_target(64, p["r_inner"], seed=3)
+    og = oracle.Geometry(p)
+    g = gpu_geom(p)
+    P = g.forward(to_dev(t, tdt), out_dtype=tdt)
+    Po = oracle.forward(og, t)
+    e_f = relL2(P.float().cpu().numpy(), Po)
+    # adjoint of stored reduced-precision projections (input rounding only)
+    y = Po / Po.max()
+    D = g.back(to_dev(y, tdt)).cpu().numpy()
+    e_a = relL2(D, oracle.adjoint(og, y))
+    say(dt, "rel-L2 forward %.3e adjoint %.3e bound %.3e" % (e_f, e_a, bound))
+    assert e_f <= bound and e_a <= bound
+    g.close()
+
+
+# ------------------------------------------- full c2 size, sampled outputs --
+
+@pytest.fixture(scope="module")
+def c2_full():
+    p = synth.workload("c2")
+    t, _ = synth.random_config2_target(256, p["r_inner"], seed=0)
+    g = gpu_geom(p)
+    yield p, t, g
+    g.close()
+
+
+def test_c2_full_forward_sampled(c2_full):
+    p, t, g = c2_full
+    say("c2 full forward, 360 angles")
+    P = g.forward(to_dev(t)).cpu().numpy()
+    assert np.isfinite(P).all()
+    rng = synth.SplitMix64(21)
+    ang = np.repeat([0, 45, 137, 359], 96)
+    vv = (rng.uniform(len(ang)) * 256).astype(np.int32)
+    uu = (rng.uniform(len(ang)) * 256).astype(np.int32)
+    ref = oracle.forward_pixels(oracle.Geometry(p), t, ang, vv, uu)
+    got = P[ang, vv, uu]
+    e = relL2(got, ref)
+    say("c2 sampled forward rel-L2 %.3e over %d pixels" % (e, len(ang)))
+    assert e <= 1e-5
+
+
+def test_c2_full_adjoint_one_angle(c2_full):
+    p, t, g = c2_full
+    rng = synth.SplitMix64(22)
+    y = rng.uniform(256 * 256).reshape(1, 256, 256)
+    say("c2 full adjoint, angle 37")
+    D = g.back(to_dev(y), angle_begin=37).cpu().numpy()
+    ref = oracle.adjoint(oracle.Geometry(p), y, a0=37, na=1)
+    e = relL2(D, ref)
+    say("c2 one-angle adjoint rel-L2 %.3e" % e)
+    assert e <= 1e-5
+
+
+def test_c2_full_adjoint_identity(c2_full):
+    p, t, g = c2_full
+    rng = synth.SplitMix64(23)
+    x = to_dev(t)
+    y = torch.from_numpy(rng.uniform(360 * 256 * 256).reshape(360, 256, 256).astype(np.float32)).to(DEV)
+    say("c2 full adjoint identity, 360 angles")
+    Ax = g.forward(x).double()
+    Aty = g.back(y).double()
+    lhs = float((Ax * y.double()).sum())
+    rhs = float((x.double() * Aty).sum())
+    scale = float(Ax.norm() * y.double().norm())
+    say("<Ax,y> %.9e  <x,A^T y> %.9e  rel %.3e" % (lhs, rhs, abs(lhs - rhs) / scale))
+    assert abs(lhs - rhs) <= 1e-6 * scale
+
+
+# --------------------------------------------------- optimisation step ----
+
+def test_optimize_step_matches_oracle_loss_and_gradient():
+    p = scaled(synth.workload("c1"), n_angles=30)
+    t, _ = synth.random_config1_target(64, 32.0, seed=4)
+    og = oracle.Geometry(p)
+    # start from scaled projections of the target
+    P0 = oracle.forward(og, t)
+    D0 = oracle.adjoint(og, P0)
+    g0 = P0 * (1.0 / np.percentile(D0[t > 0], 50))
+    loss_o, dose_o, grad_o = oracle.loss_grad(og, t, g0, 20.0, 0.8)
+    g = gpu_geom(p)
+    gp = to_dev(g0)
+    dose = torch.empty(g.vol_shape, device=DEV)
+    lr = 0.5
+    loss = g.optimize_step(to_dev(t), gp, threshold=0.8, sharpness=20.0, lr=lr, dose=dose)
+    say("loss gpu %.9e oracle %.9e" % (loss, loss_o))
+    assert loss == pytest.approx(loss_o, rel=1e-5)
+    assert relL2(dose.cpu().numpy(), dose_o) <= 1e-5
+    expect = np.maximum(g0 - lr * grad_o, 0)
+    # compare the step actually taken, where the clamp is inactive
+    step_g = g0 - gp.double().cpu().numpy()
+    step_o = g0 - expect
+    free = expect > 0
+    e = relL2(step_g[free], step_o[free])
+    say("gradient step rel-L2 %.3e" % e)
+    assert e <= 1e-4
+    g.close()
