@@ -86,6 +86,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--adjoint-variant", type=int, default=0)
+    ap.add_argument("--forward-variant", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0)
     args = ap.parse_args()
@@ -112,6 +113,7 @@ def main():
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t_setup
     g.set_adjoint_variant(args.adjoint_variant)
+    g.set_forward_variant(args.forward_variant)
     rays_hit, samples_per_pass = g.stats()
     vol = torch.from_numpy(target).to(dev)
     proj = torch.empty(g.proj_shape, device=dev)
@@ -161,7 +163,8 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic (seeded union of spheres/boxes/tori, seed %d)" % args.seed,
         "config": {"workload": WORKLOAD_NAME, "samples_per_pass": samples_per_pass,
-                   "rays_hit": rays_hit, "adjoint_variant": args.adjoint_variant},
+                   "rays_hit": rays_hit, "adjoint_variant": args.adjoint_variant,
+                   "forward_variant": args.forward_variant},
         "roofline": roofline,
         "kernels_ms": {"k_forward": f_avg, "k_back": b_avg},
         "gather_model": {"bytes_per_sample": GATHER_BYTES_PER_SAMPLE, "kernel": dom,

@@ -168,10 +168,17 @@ vam_status vam_ray_table_stats(vam_geometry_t h, int64_t* rays_hit,
  * Synchronises the handle's setup stream. */
 vam_status vam_export_rays(vam_geometry_t h, double* out);
 
-/* Select the dose-deposit kernel: 0 = default (fastest measured),
- * 1 = ray-driven scatter with direct atomics, 2 = ray-driven scatter with
- * in-register run aggregation.  Other values: VAM_ERR_INVALID_ARG. */
-vam_status vam_set_adjoint_variant(vam_geometry_t h, int32_t variant);
+/* Select the kernel variant of an operator for this handle (measurement
+ * and testing; every variant computes the same operator).
+ *   op 0, forward:  0 = default (tuned), 1 = plain reference kernel.
+ *   op 1, deposit:  0 = default (fastest measured), 1 = scatter with
+ *                   direct FP32 atomics, 2 = scatter with in-register run
+ *                   aggregation (FP32 atomics), 3 = as 2 with an FP64
+ *                   accumulator, 4 = tuned scatter (FP32 atomics),
+ *                   5 = tuned scatter with an FP64 accumulator.
+ * FP64 accumulators are allocated on first use.  Errors:
+ * VAM_ERR_BAD_HANDLE, VAM_ERR_INVALID_ARG for an unknown op or variant. */
+vam_status vam_set_variant(vam_geometry_t h, int32_t op, int32_t variant);
 
 /* Instrumentation: device time (ms) of the main kernel of the last
  * vam_forward_project and of the last vam_back_project on this handle,

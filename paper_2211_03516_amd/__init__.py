@@ -27,7 +27,11 @@ VAM_TELECENTRIC, VAM_THIN_LENS = 0, 1
 VAM_NO_FRESNEL = 1
 RAY_FIELDS = 12
 
-ADJ_DEFAULT, ADJ_SCATTER_DIRECT, ADJ_SCATTER_AGGREGATED = 0, 1, 2
+OP_FORWARD, OP_DEPOSIT = 0, 1
+FWD_DEFAULT, FWD_PLAIN = 0, 1
+ADJ_DEFAULT, ADJ_SCATTER_DIRECT, ADJ_SCATTER_AGGREGATED, ADJ_SCATTER_FP64 = 0, 1, 2, 3
+ADJ_TUNED_FP32, ADJ_TUNED_FP64 = 4, 5
+ADJ_BOX_FP64, ADJ_BOX_FP32 = 6, 7
 
 
 class VamError(RuntimeError):
@@ -83,7 +87,7 @@ def lib():
             "vam_optimize_step": [_P, _P, _P, _P, ctypes.POINTER(OptParams), _DP, _P],
             "vam_ray_table_stats": [_P, _I64P, _I64P],
             "vam_export_rays": [_P, _DP],
-            "vam_set_adjoint_variant": [_P, _I32],
+            "vam_set_variant": [_P, _I32, _I32],
             "vam_kernel_times": [_P, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)],
         }
         for name, args in sig.items():
@@ -221,7 +225,10 @@ class Geometry:
         return out
 
     def set_adjoint_variant(self, variant):
-        _check(lib().vam_set_adjoint_variant(self.handle, int(variant)))
+        _check(lib().vam_set_variant(self.handle, OP_DEPOSIT, int(variant)))
+
+    def set_forward_variant(self, variant):
+        _check(lib().vam_set_variant(self.handle, OP_FORWARD, int(variant)))
 
     def forward(self, vol, out=None, angle_begin=0, angle_count=None, out_dtype=None, stream=None):
         """Projections [angle_count, nv, nu] of vol [nz, ny, nx]."""

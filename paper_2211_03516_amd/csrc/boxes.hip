@@ -1,0 +1,322 @@
+// Lab-box tiling of the dose deposit (Sec. 2.5 of Webber et al.).
+//
+// The vial turns about +z, so every ray sample has a fixed position in the
+// lab frame; only its volume-frame position depends on the angle.  At setup
+// the resin samples of every ray are cut into segments, one per lab-frame
+// box of B^3 voxels that they cross.  The deposit then runs one workgroup
+// per (box, angle): the box, rotated into the volume frame, covers a small
+// footprint of the padded grid (at most ~(B sqrt 2 + 3)^2 (B + 3) cells),
+// which the workgroup accumulates in LDS with LDS atomics while it marches
+// all segments of the box -- about 40 samples per voxel at the full-optics
+// workload, i.e. ~320 corner deposits per cell -- and then adds to the
+// global FP64 accumulator once per cell.  The per-sample work (position,
+// weights, attenuation) is the same as in the ray-driven kernels; only the
+// place the eight corner deposits land changes, from global atomics to LDS.
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "vam_internal.h"
+
+namespace vam {
+
+constexpr int kBox = 16;
+
+__device__ inline int box_of(const BoxGrid& G, double x, double y, double z) {
+  int bx = (int)floor((x - G.x0) / G.B);
+  int by = (int)floor((y - G.y0) / G.B);
+  int bz = (int)floor((z - G.z0) / G.B);
+  bx = min(max(bx, 0), G.nbx - 1);
+  by = min(max(by, 0), G.nby - 1);
+  bz = min(max(bz, 0), G.nbz - 1);
+  return (bz * G.nby + by) * G.nbx + bx;
+}
+
+// Walk the z-clipped samples of every ray in the lab frame (FP64) and call
+// emit(box, first k, count) once per maximal run of samples in one box.
+template <class F>
+__device__ inline void walk_segments(const BoxGrid& G, const RayRec& R, const double* o, double step,
+                                     F emit) {
+  if (R.n <= 0) return;
+  int cur = -1, start = 0;
+  for (int k = R.k0; k < R.k0 + R.n; ++k) {
+    const double s = (k + 0.5) * step;
+    const int b = box_of(G, o[0] + s * o[3], o[1] + s * o[4], o[2] + s * o[5]);
+    if (b != cur) {
+      if (cur >= 0) emit(cur, start, k - start);
+      cur = b;
+      start = k;
+    }
+  }
+  if (cur >= 0) emit(cur, start, R.k0 + R.n - start);
+}
+
+__global__ void k_seg_count(BoxGrid G, const RayRec* rays, const double* ray64, int64_t n_rays, double step,
+                            int* box_count) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n_rays) return;
+  walk_segments(G, rays[r], ray64 + r * kRay64Fields, step,
+                [&](int b, int, int) { atomicAdd(box_count + b, 1); });
+}
+
+__global__ void k_seg_fill(BoxGrid G, const RayRec* rays, const double* ray64, int64_t n_rays, double step,
+                           const int* box_off, int* cursor, int2* segs) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n_rays) return;
+  walk_segments(G, rays[r], ray64 + r * kRay64Fields, step, [&](int b, int k, int n) {
+    const int slot = box_off[b] + atomicAdd(cursor + b, 1);
+    segs[slot] = make_int2((int)r, k | (n << 16));
+  });
+}
+
+struct BoxParams {
+  BoxGrid G;
+  const int2* segs;
+  const int* box_begin;
+  const int* box_id;
+  int wxy_max, wz_max;
+  int npix;            // n_u * n_v
+  int px, py, pz;
+};
+
+BoxParams box_params(const vam_geometry* h);
+
+vam_status build_boxes(vam_geometry* h, hipStream_t s) {
+  const vam_geometry_desc& D = h->desc;
+  BoxGrid G;
+  G.B = kBox;
+  const double R = D.r_inner + 1.0;
+  G.x0 = -R;
+  G.y0 = -R;
+  G.z0 = -(0.5 * (D.nz - 1) + kPad);  // lab z of padded grid coordinate 0
+  G.nbx = (int)std::ceil(2.0 * R / G.B);
+  G.nby = G.nbx;
+  G.nbz = (int)std::ceil((double)h->pz / G.B);
+  h->boxes = G;
+  const int nb_all = G.nbx * G.nby * G.nbz;
+
+  int* count = nullptr;
+  int* off = nullptr;
+  VAM_HIP_TRY(hipMalloc(&count, nb_all * sizeof(int)), "allocating box counts");
+  VAM_HIP_TRY(hipMalloc(&off, nb_all * sizeof(int)), "allocating box offsets");
+  auto release = [&]() {
+    (void)hipFree(count);
+    (void)hipFree(off);
+  };
+  hipError_t e = hipMemsetAsync(count, 0, nb_all * sizeof(int), s);
+  if (e != hipSuccess) {
+    release();
+    return hip_check(e, "clearing box counts");
+  }
+  const int threads = 256;
+  const unsigned blocks = (unsigned)((h->n_rays + threads - 1) / threads);
+  hipLaunchKernelGGL(k_seg_count, dim3(blocks), dim3(threads), 0, s, G, h->rays, h->ray64, h->n_rays,
+                     D.step, count);
+  std::vector<int> hc(nb_all);
+  e = hipGetLastError();
+  if (e == hipSuccess) e = hipMemcpyAsync(hc.data(), count, nb_all * sizeof(int), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    release();
+    return hip_check(e, "counting box segments");
+  }
+  std::vector<int> hoff(nb_all), begin, ids;
+  int64_t total = 0;
+  for (int b = 0; b < nb_all; ++b) {
+    hoff[b] = (int)total;
+    if (hc[b] > 0) {
+      ids.push_back(b);
+      begin.push_back((int)total);
+    }
+    total += hc[b];
+  }
+  begin.push_back((int)total);
+  if (total >= 0x7fffffffLL) {
+    release();
+    return fail(VAM_ERR_UNSUPPORTED, "more than 2^31 ray segments");
+  }
+  h->n_boxes = (int)ids.size();
+  h->n_segments = total;
+  e = hipMalloc(&h->segs, std::max<int64_t>(total, 1) * sizeof(int2));
+  if (e == hipSuccess) e = hipMalloc(&h->box_begin, begin.size() * sizeof(int));
+  if (e == hipSuccess) e = hipMalloc(&h->box_id, std::max<size_t>(ids.size(), 1) * sizeof(int));
+  if (e == hipSuccess) e = hipMemcpyAsync(off, hoff.data(), nb_all * sizeof(int), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(h->box_begin, begin.data(), begin.size() * sizeof(int), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess && !ids.empty())
+    e = hipMemcpyAsync(h->box_id, ids.data(), ids.size() * sizeof(int), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemsetAsync(count, 0, nb_all * sizeof(int), s);
+  if (e != hipSuccess) {
+    release();
+    return hip_check(e, "allocating box segments");
+  }
+  hipLaunchKernelGGL(k_seg_fill, dim3(blocks), dim3(threads), 0, s, G, h->rays, h->ray64, h->n_rays, D.step,
+                     off, count, h->segs);
+  e = hipGetLastError();
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  release();
+  if (e != hipSuccess) return hip_check(e, "filling box segments");
+  // largest footprint of a rotated box: extent B(|cos| + |sin|) <= B sqrt 2
+  // in x and y, B in z, plus the rounding margin and the +1 corner
+  const BoxParams Bp = box_params(h);
+  h->box_cells = Bp.wxy_max * Bp.wxy_max * Bp.wz_max;
+  return VAM_OK;
+}
+
+// --------------------------------------------------------------- deposit --
+
+
+
+template <typename PT>
+__device__ inline float load_p(const PT* p, int64_t i);
+template <>
+__device__ inline float load_p<float>(const float* p, int64_t i) { return p[i]; }
+template <>
+__device__ inline float load_p<uint16_t>(const uint16_t* p, int64_t i) {
+  return __uint_as_float((uint32_t)p[i] << 16);
+}
+template <>
+__device__ inline float load_p<__half>(const __half* p, int64_t i) { return __half2float(p[i]); }
+
+// Rotated-box footprint [X0, X1) x [Y0, Y1) x [Z0, Z1) in padded grid cells.
+struct Foot {
+  int X0, Y0, Z0, WX, WY, WZ;
+};
+
+__device__ inline Foot footprint(const BoxParams& Bp, int box, double c, double s, double cx, double cy) {
+  const BoxGrid& G = Bp.G;
+  const int bx = box % G.nbx, by = (box / G.nbx) % G.nby, bz = box / (G.nbx * G.nby);
+  const double xa = G.x0 + bx * G.B, ya = G.y0 + by * G.B;
+  double gxmin = 1e300, gxmax = -1e300, gymin = 1e300, gymax = -1e300;
+  for (int q = 0; q < 4; ++q) {
+    const double x = xa + (q & 1) * G.B, y = ya + (q >> 1) * G.B;
+    const double gx = c * x + s * y + cx, gy = -s * x + c * y + cy;
+    gxmin = fmin(gxmin, gx);
+    gxmax = fmax(gxmax, gx);
+    gymin = fmin(gymin, gy);
+    gymax = fmax(gymax, gy);
+  }
+  // [lo, hi) clamped inside the padded grid, at least 2 and at most wmax
+  // cells wide; a box outside the grid maps onto the padding at its edge
+  auto range = [](double gmin, double gmax, int n, int wmax, int& lo, int& w) {
+    lo = min(max((int)floor(gmin - 0.01), 0), n - 2);
+    int hi = min(min((int)floor(gmax + 0.01) + 2, n), lo + wmax);
+    w = max(hi, lo + 2) - lo;
+  };
+  Foot f;
+  range(gxmin, gxmax, Bp.px, Bp.wxy_max, f.X0, f.WX);
+  range(gymin, gymax, Bp.py, Bp.wxy_max, f.Y0, f.WY);
+  range((double)(bz * G.B), (double)((bz + 1) * G.B), Bp.pz, Bp.wz_max, f.Z0, f.WZ);
+  return f;
+}
+
+template <typename PT, typename AT>
+__global__ __launch_bounds__(256) void k_back_box(MarchParams P, BoxParams Bp, const PT* __restrict__ proj,
+                                                  AT* __restrict__ dose) {
+  extern __shared__ float acc[];
+  const int b = blockIdx.x;
+  const int a = blockIdx.y;
+  const int box = Bp.box_id[b];
+  const double2 cs = P.cs[P.a0 + a];
+  const Foot f = footprint(Bp, box, cs.x, cs.y, P.cx, P.cy);
+  const int ncell = f.WX * f.WY * f.WZ;
+  for (int i = threadIdx.x; i < ncell; i += blockDim.x) acc[i] = 0.0f;
+  __syncthreads();
+
+  // positions are clamped into the footprint (they lie inside it up to
+  // rounding), so every LDS index is in range
+  const float lox = (float)f.X0, hix = (float)(f.X0 + f.WX) - 1.001f;
+  const float loy = (float)f.Y0, hiy = (float)(f.Y0 + f.WY) - 1.001f;
+  const float loz = (float)f.Z0, hiz = (float)(f.Z0 + f.WZ) - 1.001f;
+  const int sy = f.WX, sz = f.WX * f.WY;
+  const int64_t pbase = (int64_t)a * Bp.npix;
+  const int s_end = Bp.box_begin[b + 1];
+  for (int si = Bp.box_begin[b] + threadIdx.x; si < s_end; si += blockDim.x) {
+    const int2 sg = Bp.segs[si];
+    const int r = sg.x, kb = sg.y & 0xffff, cnt = sg.y >> 16;
+    const float pv = load_p(proj, pbase + r % Bp.npix);
+    if (pv == 0.0f) continue;
+    const RayRec R = P.rays[r];
+    const float gx = (float)(cs.x * R.mx + cs.y * R.my + P.cx);
+    const float gy = (float)(-cs.y * R.mx + cs.x * R.my + P.cy);
+    const float dx = (float)(cs.x * R.dx + cs.y * R.dy);
+    const float dy = (float)(-cs.y * R.dx + cs.x * R.dy);
+    const float tb = fmaf((float)(kb - R.k0), P.step, R.t0);
+    float e = R.cw * pv * __builtin_amdgcn_exp2f(P.nb * tb);
+    float kf = 0.0f;
+    for (int k = 0; k < cnt; ++k, kf += 1.0f) {
+      const float t = fmaf(kf, P.step, tb);
+      const float x = __builtin_amdgcn_fmed3f(fmaf(t, dx, gx), lox, hix);
+      const float y = __builtin_amdgcn_fmed3f(fmaf(t, dy, gy), loy, hiy);
+      const float z = __builtin_amdgcn_fmed3f(fmaf(t, R.dz, R.gz), loz, hiz);
+      const float fx = __builtin_amdgcn_fractf(x), fy = __builtin_amdgcn_fractf(y),
+                  fz = __builtin_amdgcn_fractf(z);
+      const int i = ((int)z - f.Z0) * sz + ((int)y - f.Y0) * sy + ((int)x - f.X0);
+      const float z1 = e * fz, z0 = e - z1;
+      const float y01 = z0 * fy, y00 = z0 - y01;
+      const float y11 = z1 * fy, y10 = z1 - y11;
+      float* p = acc + i;
+      atomicAdd(p, y00 - y00 * fx);
+      atomicAdd(p + 1, y00 * fx);
+      atomicAdd(p + sy, y01 - y01 * fx);
+      atomicAdd(p + sy + 1, y01 * fx);
+      atomicAdd(p + sz, y10 - y10 * fx);
+      atomicAdd(p + sz + 1, y10 * fx);
+      atomicAdd(p + sz + sy, y11 - y11 * fx);
+      atomicAdd(p + sz + sy + 1, y11 * fx);
+      e = fmaf(e, P.r_hi, e * P.r_lo);
+    }
+  }
+  __syncthreads();
+  // one global add per touched cell
+  const int plane = f.WX * f.WY;
+  for (int i = threadIdx.x; i < ncell; i += blockDim.x) {
+    const float v = acc[i];
+    if (v == 0.0f) continue;
+    const int z = i / plane, rem = i - z * plane, y = rem / f.WX, x = rem - y * f.WX;
+    const int64_t gi = ((int64_t)(f.Z0 + z) * Bp.py + (f.Y0 + y)) * Bp.px + (f.X0 + x);
+    unsafeAtomicAdd(dose + gi, (AT)v);
+  }
+}
+
+BoxParams box_params(const vam_geometry* h) {
+  BoxParams Bp;
+  Bp.G = h->boxes;
+  Bp.segs = h->segs;
+  Bp.box_begin = h->box_begin;
+  Bp.box_id = h->box_id;
+  // a rotated box spans at most B sqrt 2 cells in x and y and B in z; the
+  // footprint adds the rounding margin and the +1 corner: extent + 3.02
+  Bp.wxy_max = std::min((int)std::floor(h->boxes.B * std::sqrt(2.0) + 3.02), std::max(h->px, h->py));
+  Bp.wz_max = std::min(h->boxes.B + 3, h->pz);
+  Bp.npix = h->desc.n_u * h->desc.n_v;
+  Bp.px = h->px;
+  Bp.py = h->py;
+  Bp.pz = h->pz;
+  return Bp;
+}
+
+template <typename PT>
+static void launch_box_t(vam_geometry* h, const MarchParams& P, const PT* proj, int na, bool wide,
+                         hipStream_t s) {
+  const BoxParams Bp = box_params(h);
+  const dim3 grid(h->n_boxes, na);
+  const size_t lds = (size_t)h->box_cells * sizeof(float);
+  if (wide)
+    hipLaunchKernelGGL((k_back_box<PT, double>), grid, dim3(256), lds, s, P, Bp, proj, h->dose_pad64);
+  else
+    hipLaunchKernelGGL((k_back_box<PT, float>), grid, dim3(256), lds, s, P, Bp, proj, h->dose_pad);
+}
+
+void launch_box_deposit(vam_geometry* h, const MarchParams& P, const void* proj, vam_dtype proj_t, int na,
+                        bool wide, hipStream_t s) {
+  if (h->n_boxes == 0) return;
+  switch (proj_t) {
+    case VAM_F32: launch_box_t(h, P, (const float*)proj, na, wide, s); break;
+    case VAM_BF16: launch_box_t(h, P, (const uint16_t*)proj, na, wide, s); break;
+    case VAM_F16: launch_box_t(h, P, (const __half*)proj, na, wide, s); break;
+  }
+}
+
+}  // namespace vam

@@ -32,19 +32,7 @@
 
 namespace vam {
 
-struct MarchParams {
-  const RayRec* rays;
-  const double2* cs;   // (cos, sin) per angle
-  int nu, nv, np;
-  int a0;
-  int sx;              // padded x stride
-  int sxy;             // padded slice stride
-  double cx, cy;       // centre offsets into padded x, y
-  float hix, hiy;      // clip upper bounds: n + 2.5
-  float clx, cly, clz; // clamp upper bounds: n + 2.5
-  float step;
-  float nb;            // -alpha log2(e)
-};
+
 
 // --------------------------------------------------------- element access --
 
@@ -175,9 +163,9 @@ __global__ __launch_bounds__(256) void k_forward(MarchParams P, const float* __r
 // accumulator.  AGG = true keeps the 8 corner sums of the current cell in
 // registers while consecutive samples of a ray stay in one cell and flushes
 // them when the cell changes.
-template <typename PT, bool AGG>
+template <typename PT, bool AGG, typename AT>
 __global__ __launch_bounds__(256) void k_back(MarchParams P, const PT* __restrict__ proj,
-                                              float* __restrict__ dose) {
+                                              AT* __restrict__ dose) {
   const int u = blockIdx.x * 64 + threadIdx.x;
   const int v = blockIdx.y * 4 + threadIdx.y;
   const int a = blockIdx.z;
@@ -193,7 +181,7 @@ __global__ __launch_bounds__(256) void k_back(MarchParams P, const PT* __restric
     const float scale = g.cw * pv;
     float kf = (float)g.k0;
     int cur = -1;
-    float w[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    AT w[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     for (int k = g.k0; k < g.k1; ++k, kf += 1.0f) {
       const float t = fmaf(kf, P.step, g.t0);
       float fx, fy, fz;
@@ -207,7 +195,7 @@ __global__ __launch_bounds__(256) void k_back(MarchParams P, const PT* __restric
       if (AGG) {
         if (i != cur) {
           if (cur >= 0) {
-            float* d = dose + cur;
+            AT* d = dose + cur;
             unsafeAtomicAdd(d, w[0]);
             unsafeAtomicAdd(d + 1, w[1]);
             unsafeAtomicAdd(d + P.sx, w[2]);
@@ -225,19 +213,19 @@ __global__ __launch_bounds__(256) void k_back(MarchParams P, const PT* __restric
           for (int c = 0; c < 8; ++c) w[c] += q[c];
         }
       } else {
-        float* d = dose + i;
-        unsafeAtomicAdd(d, q[0]);
-        unsafeAtomicAdd(d + 1, q[1]);
-        unsafeAtomicAdd(d + P.sx, q[2]);
-        unsafeAtomicAdd(d + P.sx + 1, q[3]);
-        unsafeAtomicAdd(d + P.sxy, q[4]);
-        unsafeAtomicAdd(d + P.sxy + 1, q[5]);
-        unsafeAtomicAdd(d + P.sxy + P.sx, q[6]);
-        unsafeAtomicAdd(d + P.sxy + P.sx + 1, q[7]);
+        AT* d = dose + i;
+        unsafeAtomicAdd(d, (AT)q[0]);
+        unsafeAtomicAdd(d + 1, (AT)q[1]);
+        unsafeAtomicAdd(d + P.sx, (AT)q[2]);
+        unsafeAtomicAdd(d + P.sx + 1, (AT)q[3]);
+        unsafeAtomicAdd(d + P.sxy, (AT)q[4]);
+        unsafeAtomicAdd(d + P.sxy + 1, (AT)q[5]);
+        unsafeAtomicAdd(d + P.sxy + P.sx, (AT)q[6]);
+        unsafeAtomicAdd(d + P.sxy + P.sx + 1, (AT)q[7]);
       }
     }
     if (AGG && cur >= 0) {
-      float* d = dose + cur;
+      AT* d = dose + cur;
       unsafeAtomicAdd(d, w[0]);
       unsafeAtomicAdd(d + 1, w[1]);
       unsafeAtomicAdd(d + P.sx, w[2]);
@@ -247,6 +235,154 @@ __global__ __launch_bounds__(256) void k_back(MarchParams P, const PT* __restric
       unsafeAtomicAdd(d + P.sxy + P.sx, w[6]);
       unsafeAtomicAdd(d + P.sxy + P.sx + 1, w[7]);
     }
+  }
+}
+
+// ---------------------------------------------------- tuned kernels (v2) --
+//
+// Same lanes, samples and weights as above, with cheaper per-sample work:
+//  * the padded working arrays are addressed through buffer resources, so a
+//    sample needs one 32-bit byte offset and the corner rows come from
+//    uniform (scalar) offsets instead of 64-bit address arithmetic; the two
+//    x-neighbours of a corner row are one 8-byte load;
+//  * positions are non-negative after the clamp, so truncation is the floor
+//    and v_fract gives the offset;
+//  * the attenuation of consecutive samples is a geometric sequence with
+//    ratio r = exp(-alpha step).  The forward sum is evaluated by Horner's
+//    rule from the far end, S <- S r + val, and the deposit keeps
+//    e <- e r; r is applied as r_hi + r_lo (two FMAs), so the rounding of r
+//    itself does not accumulate along the ray.  One exp2 per ray segment.
+
+__device__ inline __amdgpu_buffer_rsrc_t rsrc(const void* p, int bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, bytes, 0x00020000);
+}
+
+__device__ inline float2 ld_pair(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  auto a = __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0);
+  return make_float2(__uint_as_float(a[0]), __uint_as_float(a[1]));
+}
+
+// Byte offset of the base voxel of a sample and its fractional offsets.
+__device__ inline int cell4(const MarchParams& P, const Seg& g, float t, float& fx, float& fy, float& fz) {
+  const float x = __builtin_amdgcn_fmed3f(fmaf(t, g.dx, g.gx), 0.0f, P.clx);
+  const float y = __builtin_amdgcn_fmed3f(fmaf(t, g.dy, g.gy), 0.0f, P.cly);
+  const float z = __builtin_amdgcn_fmed3f(fmaf(t, g.dz, g.gz), 0.0f, P.clz);
+  fx = __builtin_amdgcn_fractf(x);
+  fy = __builtin_amdgcn_fractf(y);
+  fz = __builtin_amdgcn_fractf(z);
+  const unsigned ix = (unsigned)x, iy = (unsigned)y, iz = (unsigned)z;
+  return (int)(__umul24(iz, (unsigned)P.sxy4) + __umul24(iy, (unsigned)P.sx4) + (ix << 2));
+}
+
+template <typename PT>
+__global__ __launch_bounds__(256) void k_forward2(MarchParams P, const float* __restrict__ vol,
+                                                  PT* __restrict__ proj) {
+  const int u = blockIdx.x * 64 + threadIdx.x;
+  const int v = blockIdx.y * 4 + threadIdx.y;
+  const int a = blockIdx.z;
+  if (u >= P.nu || v >= P.nv) return;
+  const __amdgpu_buffer_rsrc_t R4 = rsrc(vol, P.vol_bytes);
+  const double2 cs = P.cs[P.a0 + a];
+  const int64_t plane = (int64_t)P.nv * P.nu;
+  const int o1 = P.sx4, o2 = P.sxy4, o3 = P.sxy4 + P.sx4;
+  float acc = 0.0f;
+  for (int j = 0; j < P.np; ++j) {
+    const RayRec R = P.rays[j * plane + (int64_t)v * P.nu + u];
+    Seg g;
+    if (!segment(P, R, cs.x, cs.y, g)) continue;
+    float S = 0.0f;
+    float kf = (float)(g.k1 - 1);
+    for (int k = g.k1 - 1; k >= g.k0; --k, kf -= 1.0f) {
+      const float t = fmaf(kf, P.step, g.t0);
+      float fx, fy, fz;
+      const int off = cell4(P, g, t, fx, fy, fz);
+      const float2 a0 = ld_pair(R4, off, 0);
+      const float2 a1 = ld_pair(R4, off, o1);
+      const float2 a2 = ld_pair(R4, off, o2);
+      const float2 a3 = ld_pair(R4, off, o3);
+      const float c00 = fmaf(fx, a0.y - a0.x, a0.x);
+      const float c01 = fmaf(fx, a1.y - a1.x, a1.x);
+      const float c10 = fmaf(fx, a2.y - a2.x, a2.x);
+      const float c11 = fmaf(fx, a3.y - a3.x, a3.x);
+      const float c0 = fmaf(fy, c01 - c00, c00);
+      const float c1 = fmaf(fy, c11 - c10, c10);
+      const float val = fmaf(fz, c1 - c0, c0);
+      S = fmaf(S, P.r_hi, fmaf(S, P.r_lo, val));
+    }
+    const float t_first = fmaf((float)g.k0, P.step, g.t0);
+    acc = fmaf(g.cw * __builtin_amdgcn_exp2f(P.nb * t_first), S, acc);
+  }
+  store_elem(proj, ((int64_t)a * P.nv + v) * P.nu + u, acc);
+}
+
+// Deposit with FP32 buffer atomics (AT = float) or FP64 global atomics
+// (AT = double), aggregating consecutive samples that share a cell.
+template <typename AT>
+__device__ inline void flush8(AT* dose, __amdgpu_buffer_rsrc_t R4, int off, const MarchParams& P,
+                              const AT* w) {
+  if constexpr (sizeof(AT) == 4) {
+    __builtin_amdgcn_raw_ptr_buffer_atomic_fadd_f32(w[0], R4, off, 0, 0);
+    __builtin_amdgcn_raw_ptr_buffer_atomic_fadd_f32(w[1], R4, off + 4, 0, 0);
+    __builtin_amdgcn_raw_ptr_buffer_atomic_fadd_f32(w[2], R4, off, P.sx4, 0);
+    __builtin_amdgcn_raw_ptr_buffer_atomic_fadd_f32(w[3], R4, off + 4, P.sx4, 0);
+    __builtin_amdgcn_raw_ptr_buffer_atomic_fadd_f32(w[4], R4, off, P.sxy4, 0);
+    __builtin_amdgcn_raw_ptr_buffer_atomic_fadd_f32(w[5], R4, off + 4, P.sxy4, 0);
+    __builtin_amdgcn_raw_ptr_buffer_atomic_fadd_f32(w[6], R4, off, P.sxy4 + P.sx4, 0);
+    __builtin_amdgcn_raw_ptr_buffer_atomic_fadd_f32(w[7], R4, off + 4, P.sxy4 + P.sx4, 0);
+  } else {
+    AT* d = dose + (off >> 2);
+    unsafeAtomicAdd(d, w[0]);
+    unsafeAtomicAdd(d + 1, w[1]);
+    unsafeAtomicAdd(d + P.sx, w[2]);
+    unsafeAtomicAdd(d + P.sx + 1, w[3]);
+    unsafeAtomicAdd(d + P.sxy, w[4]);
+    unsafeAtomicAdd(d + P.sxy + 1, w[5]);
+    unsafeAtomicAdd(d + P.sxy + P.sx, w[6]);
+    unsafeAtomicAdd(d + P.sxy + P.sx + 1, w[7]);
+  }
+}
+
+template <typename PT, typename AT>
+__global__ __launch_bounds__(256) void k_back2(MarchParams P, const PT* __restrict__ proj,
+                                               AT* __restrict__ dose) {
+  const int u = blockIdx.x * 64 + threadIdx.x;
+  const int v = blockIdx.y * 4 + threadIdx.y;
+  const int a = blockIdx.z;
+  if (u >= P.nu || v >= P.nv) return;
+  const float pv = load_elem(proj, ((int64_t)a * P.nv + v) * P.nu + u);
+  if (pv == 0.0f) return;
+  const __amdgpu_buffer_rsrc_t R4 = rsrc(dose, P.vol_bytes);
+  const double2 cs = P.cs[P.a0 + a];
+  const int64_t plane = (int64_t)P.nv * P.nu;
+  for (int j = 0; j < P.np; ++j) {
+    const RayRec R = P.rays[j * plane + (int64_t)v * P.nu + u];
+    Seg g;
+    if (!segment(P, R, cs.x, cs.y, g)) continue;
+    float kf = (float)g.k0;
+    float e = g.cw * pv * __builtin_amdgcn_exp2f(P.nb * fmaf(kf, P.step, g.t0));
+    int cur = -1;
+    AT w[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int k = g.k0; k < g.k1; ++k, kf += 1.0f) {
+      const float t = fmaf(kf, P.step, g.t0);
+      float fx, fy, fz;
+      const int off = cell4(P, g, t, fx, fy, fz);
+      const float z1 = e * fz, z0 = e - z1;
+      const float y01 = z0 * fy, y00 = z0 - y01;
+      const float y11 = z1 * fy, y10 = z1 - y11;
+      const float q[8] = {y00 - y00 * fx, y00 * fx, y01 - y01 * fx, y01 * fx,
+                          y10 - y10 * fx, y10 * fx, y11 - y11 * fx, y11 * fx};
+      if (off != cur) {
+        if (cur >= 0) flush8<AT>(dose, R4, cur, P, w);
+        cur = off;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) w[c] = q[c];
+      } else {
+#pragma unroll
+        for (int c = 0; c < 8; ++c) w[c] += q[c];
+      }
+      e = fmaf(e, P.r_hi, e * P.r_lo);
+    }
+    if (cur >= 0) flush8<AT>(dose, R4, cur, P, w);
   }
 }
 
@@ -264,7 +400,8 @@ __global__ void k_pad(const VT* __restrict__ vol, float* __restrict__ vp, int nx
 }
 
 // Interior of the padded accumulator -> caller dose (overwrite or add).
-__global__ void k_unpad(const float* __restrict__ dp, float* __restrict__ dose, int accumulate,
+template <typename AT>
+__global__ void k_unpad(const AT* __restrict__ dp, float* __restrict__ dose, int accumulate,
                         int nx, int ny, int nz, int px, int py) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t n = (int64_t)nx * ny * nz;
@@ -272,16 +409,17 @@ __global__ void k_unpad(const float* __restrict__ dp, float* __restrict__ dose, 
   const int x = (int)(i % nx);
   const int y = (int)((i / nx) % ny);
   const int z = (int)(i / ((int64_t)nx * ny));
-  const float d = dp[((int64_t)(z + kPad) * py + (y + kPad)) * px + (x + kPad)];
-  dose[i] = accumulate ? dose[i] + d : d;
+  const AT d = dp[((int64_t)(z + kPad) * py + (y + kPad)) * px + (x + kPad)];
+  dose[i] = accumulate ? (float)(dose[i] + d) : (float)d;
 }
 
-__global__ void k_fill(float* __restrict__ p, int64_t n, float value) {
+template <typename T>
+__global__ void k_fill(T* __restrict__ p, int64_t n, T value) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = value;
 }
 
-static MarchParams march_params(const vam_geometry* h, int a0) {
+MarchParams march_params(const vam_geometry* h, int a0) {
   const vam_geometry_desc& D = h->desc;
   MarchParams P;
   P.rays = h->rays;
@@ -301,8 +439,23 @@ static MarchParams march_params(const vam_geometry* h, int a0) {
   P.clz = (float)D.nz + 2.5f;
   P.step = (float)D.step;
   P.nb = (float)(-D.alpha / std::log(2.0));
+  const double r = std::exp(-D.alpha * D.step);
+  P.r_hi = (float)r;
+  P.r_lo = (float)(r - (double)P.r_hi);
+  P.sx4 = 4 * P.sx;
+  P.sxy4 = 4 * P.sxy;
+  P.vol_bytes = (int)std::min<int64_t>(h->pad_voxels * 4, 0x7fffffff);
   return P;
 }
+
+// The tuned kernels address the padded arrays with 32-bit byte offsets and
+// 24-bit multiplies.
+static bool v2_eligible(const vam_geometry* h) {
+  return h->pad_voxels * 8 < 0x7fffffffLL && (int64_t)h->px * h->py * 4 < (1 << 24);
+}
+
+// Dose-deposit kernel used when the caller asks for the default.
+constexpr int kDefaultBackVariant = 5;
 
 static inline unsigned blocks_for(int64_t n, int threads) { return (unsigned)((n + threads - 1) / threads); }
 
@@ -328,16 +481,20 @@ vam_status launch_forward(vam_geometry* h, const void* vol, vam_dtype vol_t, voi
   VAM_HIP_TRY(hipGetLastError(), "launching the volume copy");
   MarchParams P = march_params(h, a0);
   dim3 grid((D.n_u + 63) / 64, (D.n_v + 3) / 4, na), block(64, 4);
+  const bool v2 = h->forward_variant == 0 && v2_eligible(h);
   VAM_HIP_TRY(hipEventRecord(h->ev[0], s), "recording an event");
   switch (proj_t) {
     case VAM_F32:
-      hipLaunchKernelGGL(k_forward<float>, grid, block, 0, s, P, h->vol_pad, (float*)proj);
+      if (v2) hipLaunchKernelGGL(k_forward2<float>, grid, block, 0, s, P, h->vol_pad, (float*)proj);
+      else hipLaunchKernelGGL(k_forward<float>, grid, block, 0, s, P, h->vol_pad, (float*)proj);
       break;
     case VAM_BF16:
-      hipLaunchKernelGGL(k_forward<uint16_t>, grid, block, 0, s, P, h->vol_pad, (uint16_t*)proj);
+      if (v2) hipLaunchKernelGGL(k_forward2<uint16_t>, grid, block, 0, s, P, h->vol_pad, (uint16_t*)proj);
+      else hipLaunchKernelGGL(k_forward<uint16_t>, grid, block, 0, s, P, h->vol_pad, (uint16_t*)proj);
       break;
     case VAM_F16:
-      hipLaunchKernelGGL(k_forward<__half>, grid, block, 0, s, P, h->vol_pad, (__half*)proj);
+      if (v2) hipLaunchKernelGGL(k_forward2<__half>, grid, block, 0, s, P, h->vol_pad, (__half*)proj);
+      else hipLaunchKernelGGL(k_forward<__half>, grid, block, 0, s, P, h->vol_pad, (__half*)proj);
       break;
   }
   VAM_HIP_TRY(hipGetLastError(), "launching the forward projector");
@@ -347,34 +504,54 @@ vam_status launch_forward(vam_geometry* h, const void* vol, vam_dtype vol_t, voi
 }
 
 template <typename PT>
-static void launch_back_t(vam_geometry* h, const PT* proj, const MarchParams& P, dim3 grid, dim3 block,
-                          hipStream_t s) {
-  if (h->adjoint_variant == 1)
-    hipLaunchKernelGGL((k_back<PT, false>), grid, block, 0, s, P, proj, h->dose_pad);
-  else
-    hipLaunchKernelGGL((k_back<PT, true>), grid, block, 0, s, P, proj, h->dose_pad);
+static void launch_back_t(vam_geometry* h, int variant, const PT* proj, const MarchParams& P, dim3 grid,
+                          dim3 block, hipStream_t s) {
+  switch (variant) {
+    case 1: hipLaunchKernelGGL((k_back<PT, false, float>), grid, block, 0, s, P, proj, h->dose_pad); break;
+    case 2: hipLaunchKernelGGL((k_back<PT, true, float>), grid, block, 0, s, P, proj, h->dose_pad); break;
+    case 3: hipLaunchKernelGGL((k_back<PT, true, double>), grid, block, 0, s, P, proj, h->dose_pad64); break;
+    case 4: hipLaunchKernelGGL((k_back2<PT, float>), grid, block, 0, s, P, proj, h->dose_pad); break;
+    default: hipLaunchKernelGGL((k_back2<PT, double>), grid, block, 0, s, P, proj, h->dose_pad64); break;
+  }
 }
 
 vam_status launch_back(vam_geometry* h, const void* proj, vam_dtype proj_t, float* dose, int accumulate,
                        int a0, int na, hipStream_t s) {
   const vam_geometry_desc& D = h->desc;
-  hipLaunchKernelGGL(k_fill, dim3(blocks_for(h->pad_voxels, 256)), dim3(256), 0, s, h->dose_pad,
-                     h->pad_voxels, 0.0f);
+  int variant = h->adjoint_variant == 0 ? kDefaultBackVariant : h->adjoint_variant;
+  if ((variant == 4 || variant == 5) && !v2_eligible(h)) variant -= 2;
+  const bool wide = variant == 3 || variant == 5 || variant == 6;
+  if (wide && !h->dose_pad64)
+    VAM_HIP_TRY(hipMalloc(&h->dose_pad64, h->pad_voxels * sizeof(double)), "allocating the FP64 accumulator");
+  if (wide)
+    hipLaunchKernelGGL(k_fill<double>, dim3(blocks_for(h->pad_voxels, 256)), dim3(256), 0, s, h->dose_pad64,
+                       h->pad_voxels, 0.0);
+  else
+    hipLaunchKernelGGL(k_fill<float>, dim3(blocks_for(h->pad_voxels, 256)), dim3(256), 0, s, h->dose_pad,
+                       h->pad_voxels, 0.0f);
   VAM_HIP_TRY(hipGetLastError(), "launching the accumulator clear");
   MarchParams P = march_params(h, a0);
   dim3 grid((D.n_u + 63) / 64, (D.n_v + 3) / 4, na), block(64, 4);
   VAM_HIP_TRY(hipEventRecord(h->ev[2], s), "recording an event");
-  switch (proj_t) {
-    case VAM_F32: launch_back_t(h, (const float*)proj, P, grid, block, s); break;
-    case VAM_BF16: launch_back_t(h, (const uint16_t*)proj, P, grid, block, s); break;
-    case VAM_F16: launch_back_t(h, (const __half*)proj, P, grid, block, s); break;
+  if (variant >= 6) {
+    launch_box_deposit(h, P, proj, proj_t, na, wide, s);
+  } else {
+    switch (proj_t) {
+      case VAM_F32: launch_back_t(h, variant, (const float*)proj, P, grid, block, s); break;
+      case VAM_BF16: launch_back_t(h, variant, (const uint16_t*)proj, P, grid, block, s); break;
+      case VAM_F16: launch_back_t(h, variant, (const __half*)proj, P, grid, block, s); break;
+    }
   }
   VAM_HIP_TRY(hipGetLastError(), "launching the dose deposit");
   VAM_HIP_TRY(hipEventRecord(h->ev[3], s), "recording an event");
   h->ev_valid[1] = 1;
   const int64_t nvox = (int64_t)D.nx * D.ny * D.nz;
-  hipLaunchKernelGGL(k_unpad, dim3(blocks_for(nvox, 256)), dim3(256), 0, s, h->dose_pad, dose, accumulate,
-                     D.nx, D.ny, D.nz, h->px, h->py);
+  if (wide)
+    hipLaunchKernelGGL(k_unpad<double>, dim3(blocks_for(nvox, 256)), dim3(256), 0, s, h->dose_pad64, dose,
+                       accumulate, D.nx, D.ny, D.nz, h->px, h->py);
+  else
+    hipLaunchKernelGGL(k_unpad<float>, dim3(blocks_for(nvox, 256)), dim3(256), 0, s, h->dose_pad, dose,
+                       accumulate, D.nx, D.ny, D.nz, h->px, h->py);
   VAM_HIP_TRY(hipGetLastError(), "launching the dose copy");
   return VAM_OK;
 }

@@ -310,7 +310,8 @@ static vam_status validate(const vam_geometry_desc* d) {
     return bad("refractive indices must be finite and >= 1");
   if (!(d->alpha >= 0) || !std::isfinite(d->alpha)) return bad("alpha must be finite and >= 0");
   if (!(d->step > 0) || !std::isfinite(d->step)) return bad("step must be finite and > 0");
-  if (d->r_inner / d->step > 1e6) return bad("more than 2e6 samples per ray");
+  if (!(2.0 * d->r_inner / d->step < 65000.0)) return bad("more than 65000 samples per ray (2 r_inner / step)");
+  if (!(d->step >= 1e-3)) return bad("step must be >= 0.001");
   if (d->flags & ~(uint32_t)VAM_NO_FRESNEL) return bad("unknown flag bits");
   return VAM_OK;
 }
@@ -319,7 +320,8 @@ static void free_handle(vam_geometry* h) {
   if (!h) return;
   for (int i = 0; i < 4; ++i)
     if (h->ev[i]) (void)hipEventDestroy(h->ev[i]);
-  void* ptrs[] = {h->rays, h->ray64, h->angle_cs, h->vol_pad, h->dose_pad,
+  void* ptrs[] = {h->rays, h->ray64, h->angle_cs, h->vol_pad, h->dose_pad, h->dose_pad64,
+                  h->segs, h->box_begin, h->box_id,
                   h->resid, h->grad, h->dose_tmp, h->loss_part};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
@@ -427,6 +429,15 @@ vam_status vam_setup_geometry(const vam_geometry_desc* desc, hipStream_t stream,
   }
   (void)hipFree(pupil_dev);
   (void)hipFree(count_dev);
+  pupil_dev = nullptr;
+  count_dev = nullptr;
+  {
+    vam_status bs = build_boxes(h, stream);
+    if (bs != VAM_OK) {
+      free_handle(h);
+      return bs;
+    }
+  }
 #undef SETUP_TRY
   *out = h;
   return VAM_OK;
@@ -458,11 +469,18 @@ vam_status vam_export_rays(vam_geometry_t h, double* out) {
   return VAM_OK;
 }
 
-vam_status vam_set_adjoint_variant(vam_geometry_t h, int32_t variant) {
+vam_status vam_set_variant(vam_geometry_t h, int32_t op, int32_t variant) {
   clear_error();
   if (!valid_handle(h)) return fail(VAM_ERR_BAD_HANDLE, "not a live geometry handle");
-  if (variant < 0 || variant > 2) return fail(VAM_ERR_INVALID_ARG, "unknown adjoint variant %d", variant);
-  h->adjoint_variant = variant;
+  if (op == 0) {
+    if (variant < 0 || variant > 1) return fail(VAM_ERR_INVALID_ARG, "unknown forward variant %d", variant);
+    h->forward_variant = variant;
+  } else if (op == 1) {
+    if (variant < 0 || variant > 7) return fail(VAM_ERR_INVALID_ARG, "unknown deposit variant %d", variant);
+    h->adjoint_variant = variant;
+  } else {
+    return fail(VAM_ERR_INVALID_ARG, "unknown operator %d", op);
+  }
   return VAM_OK;
 }
 

@@ -37,6 +37,34 @@ struct alignas(16) RayRec {
 };
 static_assert(sizeof(RayRec) == 64, "RayRec layout");
 
+// Lab-frame boxes for the box-tiled kernels.  The resin samples of every ray
+// are split into segments, one per lab box they cross; a segment is packed
+// as (ray index, first sample k | sample count << 16).  Samples live in the
+// lab frame, so the decomposition does not depend on the angle.
+struct BoxGrid {
+  double x0, y0, z0;   // lab coordinates of the box grid origin
+  int B;               // box edge in voxels
+  int nbx, nby, nbz;
+};
+
+// Per-launch constants of the marching kernels.
+struct MarchParams {
+  const RayRec* rays;
+  const double2* cs;   // (cos, sin) per angle
+  int nu, nv, np;
+  int a0;
+  int sx;              // padded x stride
+  int sxy;             // padded slice stride
+  double cx, cy;       // centre offsets into padded x, y
+  float hix, hiy;      // clip upper bounds: n + 2.5
+  float clx, cly, clz; // clamp upper bounds: n + 2.5
+  float step;
+  float nb;            // -alpha log2(e)
+  float r_hi, r_lo;    // exp(-alpha step) split into two floats (hi + lo)
+  int sx4, sxy4;       // padded strides in bytes
+  int vol_bytes;       // size of the padded FP32 working volume in bytes
+};
+
 }  // namespace vam
 
 struct vam_geometry {
@@ -54,6 +82,7 @@ struct vam_geometry {
   double2* angle_cs;             // [n_angles] (cos, sin)
   float* vol_pad;                // padded FP32 working volume (forward input)
   float* dose_pad;               // padded FP32 dose accumulator (adjoint)
+  double* dose_pad64;            // padded FP64 accumulator, allocated on first use
   // optimisation buffers, allocated on first vam_optimize_step
   float* resid;                  // [nz][ny][nx]
   float* grad;                   // [n_angles][n_v][n_u]
@@ -63,10 +92,19 @@ struct vam_geometry {
   // events around the last forward and dose-deposit kernels (instrumentation)
   hipEvent_t ev[4];
   int ev_valid[2];
+  // lab-box segment decomposition
+  vam::BoxGrid boxes;
+  int n_boxes;                   // boxes holding at least one segment
+  int64_t n_segments;
+  int2* segs;                    // [n_segments], grouped by box
+  int* box_begin;                // [n_boxes + 1] segment offsets
+  int* box_id;                   // [n_boxes] linear box index (x fastest)
+  int box_cells;                 // largest rotated-box footprint in cells (LDS)
   // statistics
   int64_t rays_hit;
   int64_t samples_per_pass;
   int32_t adjoint_variant;
+  int32_t forward_variant;
 };
 
 namespace vam {
@@ -83,6 +121,11 @@ vam_status launch_forward(vam_geometry* h, const void* vol, vam_dtype vol_t,
 vam_status launch_back(vam_geometry* h, const void* proj, vam_dtype proj_t,
                        float* dose, int accumulate, int a0, int na,
                        hipStream_t s);
+MarchParams march_params(const vam_geometry* h, int a0);
+// lab-box decomposition and box-tiled deposit (boxes.hip)
+vam_status build_boxes(vam_geometry* h, hipStream_t s);
+void launch_box_deposit(vam_geometry* h, const MarchParams& P, const void* proj, vam_dtype proj_t, int na,
+                        bool wide, hipStream_t s);
 
 }  // namespace vam
 

@@ -64,7 +64,7 @@ def test_bad_handles_rejected(L):
     assert L.vam_back_project(None, None, 0, None, 0, 0, 1, None) == vam.VAM_ERR_BAD_HANDLE
     assert L.vam_optimize_step(None, None, None, None, None, None, None) == vam.VAM_ERR_BAD_HANDLE
     assert L.vam_export_rays(None, None) == vam.VAM_ERR_BAD_HANDLE
-    assert L.vam_set_adjoint_variant(None, 0) == vam.VAM_ERR_BAD_HANDLE
+    assert L.vam_set_variant(None, 1, 0) == vam.VAM_ERR_BAD_HANDLE
     # a pointer to garbage is not a handle either
     junk = (ctypes.c_uint64 * 64)()
     assert L.vam_ray_table_stats(ctypes.cast(junk, ctypes.c_void_p), None, None) == vam.VAM_ERR_BAD_HANDLE
