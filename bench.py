@@ -147,7 +147,7 @@ def main():
     value = 2.0 * samples_per_pass * args.steps / (total_ms * 1e-3)
 
     f_avg, b_avg = float(np.mean(fwd_ms)), float(np.mean(back_ms))
-    dom, dom_ms = ("k_back", b_avg) if b_avg >= f_avg else ("k_forward", f_avg)
+    dom, dom_ms = ("deposit", b_avg) if b_avg >= f_avg else ("forward", f_avg)
     flop = FLOP_PER_SAMPLE * samples_per_pass
     achieved = flop / (dom_ms * 1e-3) / 1e12
     traffic = load_traffic(dom)
@@ -166,7 +166,7 @@ def main():
                    "rays_hit": rays_hit, "adjoint_variant": args.adjoint_variant,
                    "forward_variant": args.forward_variant},
         "roofline": roofline,
-        "kernels_ms": {"k_forward": f_avg, "k_back": b_avg},
+        "kernels_ms": {"forward": f_avg, "deposit": b_avg},
         "gather_model": {"bytes_per_sample": GATHER_BYTES_PER_SAMPLE, "kernel": dom,
                          "GBps": gather_gbps, "frac_of_hbm_peak": gather_gbps / PEAK_HBM_GBPS},
         "setup_s": t_setup, "wall_s": wall,

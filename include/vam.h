@@ -154,6 +154,25 @@ vam_status vam_optimize_step(vam_geometry_t h, const float* target, float* proj,
                              float* dose, const vam_opt_params* params,
                              double* loss_out, hipStream_t stream);
 
+/* Ram-Lak filtering of projection rows, for the plain (filtered
+ * parallel-beam) initialisation of Sec. 2.3: each of the n_rows rows of n_u
+ * FP32 values (device, row-major) is convolved along u with the discrete
+ * band-limited ramp kernel for pixel pitch `pitch` (h[0] = 1/(4 pitch^2),
+ * h[n] = -1/(n^2 pi^2 pitch^2) for odd n, 0 for even n != 0, times pitch),
+ * then clipped at zero when clip_negative != 0.  proj_out must not alias
+ * proj_in.  Asynchronous on `stream`.  Errors: VAM_ERR_INVALID_ARG for NULL
+ * or aliased buffers, n_u outside [1, 8192], pitch <= 0. */
+vam_status vam_ramlak_filter(const float* proj_in, float* proj_out, int32_t n_rows, int32_t n_u,
+                             double pitch, int32_t clip_negative, hipStream_t stream);
+
+/* Dose error of Sec. 2.7's termination test, reduced in FP64 over n
+ * voxels of device arrays dose and target (FP32):
+ *   out2[0] = ||sigmoid(sharpness (dose - threshold)) - target||_1 / ||target||_1,
+ *   out2[1] = fraction of voxels where (dose >= threshold) != (target >= 0.5).
+ * out2 is host memory; the call synchronises `stream`. */
+vam_status vam_dose_error(const float* dose, const float* target, int64_t n, double threshold,
+                          double sharpness, double* out2, hipStream_t stream);
+
 /* Ray-table statistics: rays that reach the resin, and ray-voxel samples
  * over all angles whose anti-aliasing stencil touches the grid (one pass of
  * vam_forward_project or vam_back_project over all angles processes this
@@ -170,12 +189,16 @@ vam_status vam_export_rays(vam_geometry_t h, double* out);
 
 /* Select the kernel variant of an operator for this handle (measurement
  * and testing; every variant computes the same operator).
- *   op 0, forward:  0 = default (tuned), 1 = plain reference kernel.
+ *   op 0, forward:  0 = default (fastest measured), 1 = plain ray-driven
+ *                   kernel, 2 = lab-box tiled (volume staged in LDS),
+ *                   3 = tuned ray-driven kernel.
  *   op 1, deposit:  0 = default (fastest measured), 1 = scatter with
  *                   direct FP32 atomics, 2 = scatter with in-register run
  *                   aggregation (FP32 atomics), 3 = as 2 with an FP64
  *                   accumulator, 4 = tuned scatter (FP32 atomics),
- *                   5 = tuned scatter with an FP64 accumulator.
+ *                   5 = tuned scatter with an FP64 accumulator,
+ *                   6 = lab-box tiled, LDS accumulation, FP64 accumulator,
+ *                   7 = lab-box tiled, LDS accumulation, FP32 accumulator.
  * FP64 accumulators are allocated on first use.  Errors:
  * VAM_ERR_BAD_HANDLE, VAM_ERR_INVALID_ARG for an unknown op or variant. */
 vam_status vam_set_variant(vam_geometry_t h, int32_t op, int32_t variant);

@@ -28,7 +28,7 @@ VAM_NO_FRESNEL = 1
 RAY_FIELDS = 12
 
 OP_FORWARD, OP_DEPOSIT = 0, 1
-FWD_DEFAULT, FWD_PLAIN = 0, 1
+FWD_DEFAULT, FWD_PLAIN, FWD_BOX, FWD_TUNED = 0, 1, 2, 3
 ADJ_DEFAULT, ADJ_SCATTER_DIRECT, ADJ_SCATTER_AGGREGATED, ADJ_SCATTER_FP64 = 0, 1, 2, 3
 ADJ_TUNED_FP32, ADJ_TUNED_FP64 = 4, 5
 ADJ_BOX_FP64, ADJ_BOX_FP32 = 6, 7
@@ -89,6 +89,8 @@ def lib():
             "vam_export_rays": [_P, _DP],
             "vam_set_variant": [_P, _I32, _I32],
             "vam_kernel_times": [_P, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)],
+            "vam_ramlak_filter": [_P, _P, _I32, _I32, ctypes.c_double, _I32, _P],
+            "vam_dose_error": [_P, _P, ctypes.c_int64, ctypes.c_double, ctypes.c_double, _DP, _P],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -276,6 +278,34 @@ class Geometry:
                                        ctypes.byref(prm), ctypes.byref(loss) if want_loss else None,
                                        _stream_ptr(stream)))
         return loss.value if want_loss else None
+
+
+def ramlak_filter(proj, pitch=1.0, clip_negative=True, out=None, stream=None):
+    """Ram-Lak filter along u of every row of proj [..., nu] (FP32, device),
+    clipped at zero (the filtered back-projection step of the plain
+    initialisation)."""
+    torch = _torch()
+    _need_device_tensor(proj, "proj", None, (torch.float32,))
+    if out is None:
+        out = torch.empty_like(proj)
+    _need_device_tensor(out, "out", tuple(proj.shape), (torch.float32,))
+    nu = proj.shape[-1]
+    rows = proj.numel() // nu
+    _check(lib().vam_ramlak_filter(proj.data_ptr(), out.data_ptr(), rows, nu, float(pitch),
+                                   int(bool(clip_negative)), _stream_ptr(stream)))
+    return out
+
+
+def dose_error(dose, target, threshold=0.8, sharpness=20.0, stream=None):
+    """(relative L1 error of the sigmoid-thresholded dose, voxel error rate),
+    both reduced in FP64 on the device."""
+    torch = _torch()
+    _need_device_tensor(dose, "dose", None, (torch.float32,))
+    _need_device_tensor(target, "target", tuple(dose.shape), (torch.float32,))
+    out = (ctypes.c_double * 2)()
+    _check(lib().vam_dose_error(dose.data_ptr(), target.data_ptr(), dose.numel(), float(threshold),
+                                float(sharpness), ctypes.cast(out, _DP), _stream_ptr(stream)))
+    return out[0], out[1]
 
 
 def version():

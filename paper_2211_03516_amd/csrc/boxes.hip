@@ -34,45 +34,50 @@ __device__ inline int box_of(const BoxGrid& G, double x, double y, double z) {
 }
 
 // Walk the z-clipped samples of every ray in the lab frame (FP64) and call
-// emit(box, first k, count) once per maximal run of samples in one box.
+// emit(box, first k, count, rank) once per maximal run of samples in one
+// box; rank numbers the runs of a ray from 0 in marching order.
 template <class F>
 __device__ inline void walk_segments(const BoxGrid& G, const RayRec& R, const double* o, double step,
                                      F emit) {
   if (R.n <= 0) return;
-  int cur = -1, start = 0;
+  int cur = -1, start = 0, rank = 0;
   for (int k = R.k0; k < R.k0 + R.n; ++k) {
     const double s = (k + 0.5) * step;
     const int b = box_of(G, o[0] + s * o[3], o[1] + s * o[4], o[2] + s * o[5]);
     if (b != cur) {
-      if (cur >= 0) emit(cur, start, k - start);
+      if (cur >= 0) emit(cur, start, k - start, rank++);
       cur = b;
       start = k;
     }
   }
-  if (cur >= 0) emit(cur, start, R.k0 + R.n - start);
+  if (cur >= 0) emit(cur, start, R.k0 + R.n - start, rank);
 }
 
 __global__ void k_seg_count(BoxGrid G, const RayRec* rays, const double* ray64, int64_t n_rays, double step,
-                            int* box_count) {
+                            int* box_count, int* ray_nseg) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= n_rays) return;
-  walk_segments(G, rays[r], ray64 + r * kRay64Fields, step,
-                [&](int b, int, int) { atomicAdd(box_count + b, 1); });
+  int n = 0;
+  walk_segments(G, rays[r], ray64 + r * kRay64Fields, step, [&](int b, int, int, int) {
+    atomicAdd(box_count + b, 1);
+    ++n;
+  });
+  ray_nseg[r] = n;
 }
 
 __global__ void k_seg_fill(BoxGrid G, const RayRec* rays, const double* ray64, int64_t n_rays, double step,
-                           const int* box_off, int* cursor, int2* segs) {
+                           const int* box_off, int* cursor, int4* segs) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= n_rays) return;
-  walk_segments(G, rays[r], ray64 + r * kRay64Fields, step, [&](int b, int k, int n) {
+  walk_segments(G, rays[r], ray64 + r * kRay64Fields, step, [&](int b, int k, int n, int rank) {
     const int slot = box_off[b] + atomicAdd(cursor + b, 1);
-    segs[slot] = make_int2((int)r, k | (n << 16));
+    segs[slot] = make_int4((int)r, k, n, rank);
   });
 }
 
 struct BoxParams {
   BoxGrid G;
-  const int2* segs;
+  const int4* segs;
   const int* box_begin;
   const int* box_id;
   int wxy_max, wz_max;
@@ -100,6 +105,7 @@ vam_status build_boxes(vam_geometry* h, hipStream_t s) {
   int* off = nullptr;
   VAM_HIP_TRY(hipMalloc(&count, nb_all * sizeof(int)), "allocating box counts");
   VAM_HIP_TRY(hipMalloc(&off, nb_all * sizeof(int)), "allocating box offsets");
+  VAM_HIP_TRY(hipMalloc(&h->ray_nseg, h->n_rays * sizeof(int)), "allocating segment counts");
   auto release = [&]() {
     (void)hipFree(count);
     (void)hipFree(off);
@@ -112,7 +118,7 @@ vam_status build_boxes(vam_geometry* h, hipStream_t s) {
   const int threads = 256;
   const unsigned blocks = (unsigned)((h->n_rays + threads - 1) / threads);
   hipLaunchKernelGGL(k_seg_count, dim3(blocks), dim3(threads), 0, s, G, h->rays, h->ray64, h->n_rays,
-                     D.step, count);
+                     D.step, count, h->ray_nseg);
   std::vector<int> hc(nb_all);
   e = hipGetLastError();
   if (e == hipSuccess) e = hipMemcpyAsync(hc.data(), count, nb_all * sizeof(int), hipMemcpyDeviceToHost, s);
@@ -138,7 +144,7 @@ vam_status build_boxes(vam_geometry* h, hipStream_t s) {
   }
   h->n_boxes = (int)ids.size();
   h->n_segments = total;
-  e = hipMalloc(&h->segs, std::max<int64_t>(total, 1) * sizeof(int2));
+  e = hipMalloc(&h->segs, std::max<int64_t>(total, 1) * sizeof(int4));
   if (e == hipSuccess) e = hipMalloc(&h->box_begin, begin.size() * sizeof(int));
   if (e == hipSuccess) e = hipMalloc(&h->box_id, std::max<size_t>(ids.size(), 1) * sizeof(int));
   if (e == hipSuccess) e = hipMemcpyAsync(off, hoff.data(), nb_all * sizeof(int), hipMemcpyHostToDevice, s);
@@ -157,6 +163,23 @@ vam_status build_boxes(vam_geometry* h, hipStream_t s) {
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   release();
   if (e != hipSuccess) return hip_check(e, "filling box segments");
+  // Order each box's segments by ray: neighbouring lanes then handle
+  // neighbouring pixels (coalesced projection accesses), and the order no
+  // longer depends on the scheduling of the fill kernel.
+  {
+    std::vector<int4> hs(std::max<int64_t>(total, 1));
+    e = hipMemcpy(hs.data(), h->segs, total * sizeof(int4), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_check(e, "reading box segments");
+    for (size_t i = 0; i + 1 < begin.size(); ++i)
+      std::sort(hs.begin() + begin[i], hs.begin() + begin[i + 1],
+                [](const int4& x, const int4& y) { return x.x < y.x; });
+    e = hipMemcpy(h->segs, hs.data(), total * sizeof(int4), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_check(e, "writing box segments");
+    std::vector<int> ns(h->n_rays);
+    e = hipMemcpy(ns.data(), h->ray_nseg, h->n_rays * sizeof(int), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_check(e, "reading segment counts");
+    h->max_seg_per_ray = ns.empty() ? 0 : *std::max_element(ns.begin(), ns.end());
+  }
   // largest footprint of a rotated box: extent B(|cos| + |sin|) <= B sqrt 2
   // in x and y, B in z, plus the rounding margin and the +1 corner
   const BoxParams Bp = box_params(h);
@@ -178,6 +201,19 @@ __device__ inline float load_p<uint16_t>(const uint16_t* p, int64_t i) {
 }
 template <>
 __device__ inline float load_p<__half>(const __half* p, int64_t i) { return __half2float(p[i]); }
+
+
+__device__ inline void store_proj(float* p, int64_t i, float x) { p[i] = x; }
+__device__ inline void store_proj(uint16_t* p, int64_t i, float x) {
+  uint32_t u = __float_as_uint(x);
+  if ((u & 0x7fffffffu) > 0x7f800000u) {
+    p[i] = (uint16_t)((u >> 16) | 0x40u);
+  } else {
+    u += 0x7fffu + ((u >> 16) & 1u);
+    p[i] = (uint16_t)(u >> 16);
+  }
+}
+__device__ inline void store_proj(__half* p, int64_t i, float x) { p[i] = __float2half_rn(x); }
 
 // Rotated-box footprint [X0, X1) x [Y0, Y1) x [Z0, Z1) in padded grid cells.
 struct Foot {
@@ -233,8 +269,8 @@ __global__ __launch_bounds__(256) void k_back_box(MarchParams P, BoxParams Bp, c
   const int64_t pbase = (int64_t)a * Bp.npix;
   const int s_end = Bp.box_begin[b + 1];
   for (int si = Bp.box_begin[b] + threadIdx.x; si < s_end; si += blockDim.x) {
-    const int2 sg = Bp.segs[si];
-    const int r = sg.x, kb = sg.y & 0xffff, cnt = sg.y >> 16;
+    const int4 sg = Bp.segs[si];
+    const int r = sg.x, kb = sg.y, cnt = sg.z;
     const float pv = load_p(proj, pbase + r % Bp.npix);
     if (pv == 0.0f) continue;
     const RayRec R = P.rays[r];
@@ -317,6 +353,130 @@ void launch_box_deposit(vam_geometry* h, const MarchParams& P, const void* proj,
     case VAM_BF16: launch_box_t(h, P, (const uint16_t*)proj, na, wide, s); break;
     case VAM_F16: launch_box_t(h, P, (const __half*)proj, na, wide, s); break;
   }
+}
+
+
+// --------------------------------------------------------------- forward --
+//
+// Forward projection over the same decomposition: the workgroup of a
+// (box, angle) stages the rotated box footprint of the padded volume in LDS
+// (one coalesced read per cell), then every segment of the box gathers its
+// samples from LDS.  The segment's partial sum (Horner over its samples,
+// times the ray weight and the attenuation of its first sample) is written to
+// part[angle][rank][ray]; a second kernel adds, per pixel, the partials of
+// its rays in a fixed order (pupil index, then rank), so the result does not
+// depend on scheduling.
+
+template <typename AT>
+__global__ __launch_bounds__(256) void k_forward_box(MarchParams P, BoxParams Bp, const float* __restrict__ vol,
+                                                     float* __restrict__ part, int64_t n_rays, int smax) {
+  extern __shared__ float sv[];
+  const int b = blockIdx.x;
+  const int a = blockIdx.y;
+  const int box = Bp.box_id[b];
+  const double2 cs = P.cs[P.a0 + a];
+  const Foot f = footprint(Bp, box, cs.x, cs.y, P.cx, P.cy);
+  const int plane = f.WX * f.WY;
+  const int ncell = plane * f.WZ;
+  for (int i = threadIdx.x; i < ncell; i += blockDim.x) {
+    const int z = i / plane, rem = i - z * plane, y = rem / f.WX, x = rem - y * f.WX;
+    sv[i] = vol[((int64_t)(f.Z0 + z) * Bp.py + (f.Y0 + y)) * Bp.px + (f.X0 + x)];
+  }
+  __syncthreads();
+  const float lox = (float)f.X0, hix = (float)(f.X0 + f.WX) - 1.001f;
+  const float loy = (float)f.Y0, hiy = (float)(f.Y0 + f.WY) - 1.001f;
+  const float loz = (float)f.Z0, hiz = (float)(f.Z0 + f.WZ) - 1.001f;
+  const int sy = f.WX, sz = plane;
+  const int s_end = Bp.box_begin[b + 1];
+  float* out = part + (int64_t)a * smax * n_rays;
+  for (int si = Bp.box_begin[b] + threadIdx.x; si < s_end; si += blockDim.x) {
+    const int4 sg = Bp.segs[si];
+    const int r = sg.x, kb = sg.y, cnt = sg.z;
+    const RayRec R = P.rays[r];
+    const float gx = (float)(cs.x * R.mx + cs.y * R.my + P.cx);
+    const float gy = (float)(-cs.y * R.mx + cs.x * R.my + P.cy);
+    const float dx = (float)(cs.x * R.dx + cs.y * R.dy);
+    const float dy = (float)(-cs.y * R.dx + cs.x * R.dy);
+    const float tb = fmaf((float)(kb - R.k0), P.step, R.t0);
+    float S = 0.0f;
+    float kf = (float)(cnt - 1);
+    for (int k = cnt - 1; k >= 0; --k, kf -= 1.0f) {
+      const float t = fmaf(kf, P.step, tb);
+      const float x = __builtin_amdgcn_fmed3f(fmaf(t, dx, gx), lox, hix);
+      const float y = __builtin_amdgcn_fmed3f(fmaf(t, dy, gy), loy, hiy);
+      const float z = __builtin_amdgcn_fmed3f(fmaf(t, R.dz, R.gz), loz, hiz);
+      const float fx = __builtin_amdgcn_fractf(x), fy = __builtin_amdgcn_fractf(y),
+                  fz = __builtin_amdgcn_fractf(z);
+      const float* p = sv + (((int)z - f.Z0) * sz + ((int)y - f.Y0) * sy + ((int)x - f.X0));
+      const float c00 = fmaf(fx, p[1] - p[0], p[0]);
+      const float c01 = fmaf(fx, p[sy + 1] - p[sy], p[sy]);
+      const float c10 = fmaf(fx, p[sz + 1] - p[sz], p[sz]);
+      const float c11 = fmaf(fx, p[sz + sy + 1] - p[sz + sy], p[sz + sy]);
+      const float c0 = fmaf(fy, c01 - c00, c00);
+      const float c1 = fmaf(fy, c11 - c10, c10);
+      const float val = fmaf(fz, c1 - c0, c0);
+      S = fmaf(S, P.r_hi, fmaf(S, P.r_lo, val));
+    }
+    out[(int64_t)sg.w * n_rays + r] = R.cw * __builtin_amdgcn_exp2f(P.nb * tb) * S;
+  }
+}
+
+template <typename PT>
+__global__ void k_reduce_segments(const float* __restrict__ part, const int* __restrict__ nseg,
+                                  PT* __restrict__ proj, int npix, int np, int64_t n_rays, int smax, int na) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)na * npix) return;
+  const int a = (int)(i / npix);
+  const int pix = (int)(i - (int64_t)a * npix);
+  const float* base = part + (int64_t)a * smax * n_rays;
+  float acc = 0.0f;
+  for (int j = 0; j < np; ++j) {
+    const int64_t r = (int64_t)j * npix + pix;
+    const int ns = nseg[r];
+    float s = 0.0f;
+    for (int q = 0; q < ns; ++q) s += base[(int64_t)q * n_rays + r];
+    acc += s;
+  }
+  store_proj(proj, i, acc);
+}
+
+template <typename PT>
+static vam_status forward_box_t(vam_geometry* h, const MarchParams& P0, PT* proj, int na, hipStream_t s) {
+  const vam_geometry_desc& D = h->desc;
+  const int smax = std::max(h->max_seg_per_ray, 1);
+  const int64_t per_angle = (int64_t)smax * h->n_rays;
+  if (!h->seg_part) {
+    // partial sums for a chunk of angles, at most ~2 GiB
+    h->seg_part_angles = (int)std::max<int64_t>(1, std::min<int64_t>(D.n_angles, (int64_t(1) << 29) / per_angle));
+    VAM_HIP_TRY(hipMalloc(&h->seg_part, per_angle * h->seg_part_angles * sizeof(float)),
+                "allocating segment partial sums");
+  }
+  const BoxParams Bp = box_params(h);
+  const size_t lds = (size_t)h->box_cells * sizeof(float);
+  const int npix = D.n_u * D.n_v;
+  for (int c0 = 0; c0 < na; c0 += h->seg_part_angles) {
+    const int nc = std::min(h->seg_part_angles, na - c0);
+    MarchParams P = P0;
+    P.a0 = P0.a0 + c0;
+    if (h->n_boxes > 0)
+      hipLaunchKernelGGL((k_forward_box<float>), dim3(h->n_boxes, nc), dim3(256), lds, s, P, Bp, h->vol_pad,
+                         h->seg_part, h->n_rays, smax);
+    const int64_t n = (int64_t)nc * npix;
+    hipLaunchKernelGGL(k_reduce_segments<PT>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, h->seg_part,
+                       h->ray_nseg, proj + (int64_t)c0 * npix, npix, D.n_pupil, h->n_rays, smax, nc);
+    VAM_HIP_TRY(hipGetLastError(), "launching the box-tiled forward projector");
+  }
+  return VAM_OK;
+}
+
+vam_status launch_box_forward(vam_geometry* h, const MarchParams& P, void* proj, vam_dtype proj_t, int na,
+                              hipStream_t s) {
+  switch (proj_t) {
+    case VAM_F32: return forward_box_t(h, P, (float*)proj, na, s);
+    case VAM_BF16: return forward_box_t(h, P, (uint16_t*)proj, na, s);
+    case VAM_F16: return forward_box_t(h, P, (__half*)proj, na, s);
+  }
+  return fail(VAM_ERR_INVALID_ARG, "unknown projection dtype");
 }
 
 }  // namespace vam

@@ -454,8 +454,9 @@ static bool v2_eligible(const vam_geometry* h) {
   return h->pad_voxels * 8 < 0x7fffffffLL && (int64_t)h->px * h->py * 4 < (1 << 24);
 }
 
-// Dose-deposit kernel used when the caller asks for the default.
-constexpr int kDefaultBackVariant = 5;
+// Kernels used when the caller asks for the default (fastest measured).
+constexpr int kDefaultForwardVariant = 2;
+constexpr int kDefaultBackVariant = 6;
 
 static inline unsigned blocks_for(int64_t n, int threads) { return (unsigned)((n + threads - 1) / threads); }
 
@@ -481,8 +482,16 @@ vam_status launch_forward(vam_geometry* h, const void* vol, vam_dtype vol_t, voi
   VAM_HIP_TRY(hipGetLastError(), "launching the volume copy");
   MarchParams P = march_params(h, a0);
   dim3 grid((D.n_u + 63) / 64, (D.n_v + 3) / 4, na), block(64, 4);
-  const bool v2 = h->forward_variant == 0 && v2_eligible(h);
+  const int fv = h->forward_variant == 0 ? kDefaultForwardVariant : h->forward_variant;
+  const bool v2 = fv == 3 && v2_eligible(h);
   VAM_HIP_TRY(hipEventRecord(h->ev[0], s), "recording an event");
+  if (fv == 2) {
+    vam_status st = launch_box_forward(h, P, proj, proj_t, na, s);
+    if (st != VAM_OK) return st;
+    VAM_HIP_TRY(hipEventRecord(h->ev[1], s), "recording an event");
+    h->ev_valid[0] = 1;
+    return VAM_OK;
+  }
   switch (proj_t) {
     case VAM_F32:
       if (v2) hipLaunchKernelGGL(k_forward2<float>, grid, block, 0, s, P, h->vol_pad, (float*)proj);

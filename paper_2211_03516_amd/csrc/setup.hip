@@ -310,7 +310,7 @@ static vam_status validate(const vam_geometry_desc* d) {
     return bad("refractive indices must be finite and >= 1");
   if (!(d->alpha >= 0) || !std::isfinite(d->alpha)) return bad("alpha must be finite and >= 0");
   if (!(d->step > 0) || !std::isfinite(d->step)) return bad("step must be finite and > 0");
-  if (!(2.0 * d->r_inner / d->step < 65000.0)) return bad("more than 65000 samples per ray (2 r_inner / step)");
+  if (!(2.0 * d->r_inner / d->step < 1e6)) return bad("more than 1e6 samples per ray (2 r_inner / step)");
   if (!(d->step >= 1e-3)) return bad("step must be >= 0.001");
   if (d->flags & ~(uint32_t)VAM_NO_FRESNEL) return bad("unknown flag bits");
   return VAM_OK;
@@ -321,7 +321,7 @@ static void free_handle(vam_geometry* h) {
   for (int i = 0; i < 4; ++i)
     if (h->ev[i]) (void)hipEventDestroy(h->ev[i]);
   void* ptrs[] = {h->rays, h->ray64, h->angle_cs, h->vol_pad, h->dose_pad, h->dose_pad64,
-                  h->segs, h->box_begin, h->box_id,
+                  h->segs, h->box_begin, h->box_id, h->ray_nseg, h->seg_part,
                   h->resid, h->grad, h->dose_tmp, h->loss_part};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
@@ -473,7 +473,7 @@ vam_status vam_set_variant(vam_geometry_t h, int32_t op, int32_t variant) {
   clear_error();
   if (!valid_handle(h)) return fail(VAM_ERR_BAD_HANDLE, "not a live geometry handle");
   if (op == 0) {
-    if (variant < 0 || variant > 1) return fail(VAM_ERR_INVALID_ARG, "unknown forward variant %d", variant);
+    if (variant < 0 || variant > 3) return fail(VAM_ERR_INVALID_ARG, "unknown forward variant %d", variant);
     h->forward_variant = variant;
   } else if (op == 1) {
     if (variant < 0 || variant > 7) return fail(VAM_ERR_INVALID_ARG, "unknown deposit variant %d", variant);

@@ -38,9 +38,9 @@ struct alignas(16) RayRec {
 static_assert(sizeof(RayRec) == 64, "RayRec layout");
 
 // Lab-frame boxes for the box-tiled kernels.  The resin samples of every ray
-// are split into segments, one per lab box they cross; a segment is packed
-// as (ray index, first sample k | sample count << 16).  Samples live in the
-// lab frame, so the decomposition does not depend on the angle.
+// are split into segments, one per lab box they cross; a segment is
+// (ray index, first sample k, sample count, rank along the ray).  Samples
+// live in the lab frame, so the decomposition does not depend on the angle.
 struct BoxGrid {
   double x0, y0, z0;   // lab coordinates of the box grid origin
   int B;               // box edge in voxels
@@ -96,7 +96,11 @@ struct vam_geometry {
   vam::BoxGrid boxes;
   int n_boxes;                   // boxes holding at least one segment
   int64_t n_segments;
-  int2* segs;                    // [n_segments], grouped by box
+  int4* segs;                    // [n_segments], grouped by box, by ray within a box
+  int* ray_nseg;                 // [n_rays] segments per ray
+  int max_seg_per_ray;
+  float* seg_part;               // forward partial sums [angles][rank][ray], on first use
+  int seg_part_angles;           // angles per chunk of seg_part
   int* box_begin;                // [n_boxes + 1] segment offsets
   int* box_id;                   // [n_boxes] linear box index (x fastest)
   int box_cells;                 // largest rotated-box footprint in cells (LDS)
@@ -124,6 +128,8 @@ vam_status launch_back(vam_geometry* h, const void* proj, vam_dtype proj_t,
 MarchParams march_params(const vam_geometry* h, int a0);
 // lab-box decomposition and box-tiled deposit (boxes.hip)
 vam_status build_boxes(vam_geometry* h, hipStream_t s);
+vam_status launch_box_forward(vam_geometry* h, const MarchParams& P, void* proj, vam_dtype proj_t, int na,
+                              hipStream_t s);
 void launch_box_deposit(vam_geometry* h, const MarchParams& P, const void* proj, vam_dtype proj_t, int na,
                         bool wide, hipStream_t s);
 

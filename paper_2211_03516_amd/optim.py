@@ -1,0 +1,129 @@
+"""Projection optimisation on top of the projector pair.
+
+* `Project` / `Dose`: torch.autograd.Functions whose backward passes are the
+  library's own transposed kernels (projection <-> dose deposit), so any
+  torch loss on the dose can drive gradient descent on the projections.
+* `plain_init`: the filtered parallel-beam initialisation of the paper's
+  Radon baseline (Sec. 2.3): parallel-beam projection of the target with the
+  same grid, DMD and angles, Ram-Lak filter along u, negatives clipped, then
+  scaled so that the mean dose over target voxels is 1.
+* `optimize`: repeated `vam_optimize_step` (projected gradient on the
+  dose-threshold loss), stopping when the dose error of Sec. 2.7 falls below
+  a tolerance.
+
+Every numerical step runs in libvam's kernels; this module only sequences
+calls.
+"""
+import time
+
+import torch
+
+from . import Geometry, dose_error, ramlak_filter, VAM_TELECENTRIC
+
+
+class Project(torch.autograd.Function):
+    """P = A V (forward projection); dL/dV = A^T dL/dP (dose deposit)."""
+
+    @staticmethod
+    def forward(ctx, vol, geom):
+        ctx.geom = geom
+        return geom.forward(vol.contiguous())
+
+    @staticmethod
+    def backward(ctx, grad_p):
+        return ctx.geom.back(grad_p.contiguous().float()), None
+
+
+class Dose(torch.autograd.Function):
+    """D = A^T P (dose deposit); dL/dP = A dL/dD (forward projection)."""
+
+    @staticmethod
+    def forward(ctx, proj, geom):
+        ctx.geom = geom
+        return geom.back(proj.contiguous())
+
+    @staticmethod
+    def backward(ctx, grad_d):
+        return ctx.geom.forward(grad_d.contiguous().float()), None
+
+
+def project(vol, geom):
+    return Project.apply(vol, geom)
+
+
+def dose(proj, geom):
+    return Dose.apply(proj, geom)
+
+
+def parallel_beam_params(p):
+    """Telecentric, chief-ray-only, index-matched version of a geometry on
+    the same grid, DMD and angles (the Radon baseline's ray model)."""
+    q = dict(p)
+    q.update(projector=VAM_TELECENTRIC, pupil=0.0, n_pupil=1, pupil_xy=None,
+             r_outer=p["r_inner"], r_inner=p["r_inner"], flags=0)
+    return q
+
+
+def plain_init(target, geom, parallel=None):
+    """Filtered parallel-beam starting projections for `target` (device FP32
+    volume), scaled so that the mean dose over target voxels is 1."""
+    own = parallel is None
+    if own:
+        parallel = Geometry(parallel_beam_params(geom.p))
+    try:
+        sino = parallel.forward(target)
+        g0 = ramlak_filter(sino, pitch=geom.p["pitch_u"], clip_negative=True)
+    finally:
+        if own:
+            parallel.close()
+    d = geom.back(g0)
+    mask = target > 0.5
+    mean_dose = float(d[mask].mean()) if bool(mask.any()) else float(d.mean())
+    if mean_dose > 0:
+        g0.mul_(1.0 / mean_dose)
+    return g0
+
+
+def optimize(target, geom, proj=None, steps=50, lr=None, threshold=0.8, sharpness=20.0,
+             tol=None, check_every=1, log=None):
+    """Projected gradient descent on the dose-threshold loss.  Returns
+    (projections, history) where history holds per-step loss, dose error and
+    voxel error rate.  lr=None picks the step by backtracking on the first
+    step and keeps it fixed."""
+    if proj is None:
+        proj = plain_init(target, geom)
+    proj = proj.contiguous()
+    dose_buf = torch.empty_like(target)
+    hist = []
+    t0 = time.perf_counter()
+    if lr is None:
+        lr = _first_step(target, geom, proj, threshold, sharpness)
+    for it in range(steps):
+        loss = geom.optimize_step(target, proj, threshold=threshold, sharpness=sharpness, lr=lr,
+                                  dose=dose_buf)
+        rec = {"step": it, "loss": loss, "t": time.perf_counter() - t0}
+        if check_every and (it % check_every == 0 or it == steps - 1):
+            e, rate = dose_error(dose_buf, target, threshold, sharpness)
+            rec.update(dose_error=e, voxel_error=rate)
+            if tol is not None and e < tol:
+                hist.append(rec)
+                break
+        hist.append(rec)
+        if log:
+            log(rec)
+    return proj, hist
+
+
+def _first_step(target, geom, proj, threshold, sharpness, lr0=None, shrink=0.5, tries=12):
+    """Armijo backtracking on a copy of the projections for the first step."""
+    base = geom.optimize_step(target, proj.clone(), threshold=threshold, sharpness=sharpness, lr=0.0)
+    # scale of the gradient: one step with lr = 1 on a scratch copy
+    lr = lr0 if lr0 is not None else 1.0 / max(base, 1e-12)
+    for _ in range(tries):
+        trial = proj.clone()
+        geom.optimize_step(target, trial, threshold=threshold, sharpness=sharpness, lr=lr, want_loss=False)
+        after = geom.optimize_step(target, trial.clone(), threshold=threshold, sharpness=sharpness, lr=0.0)
+        if after < base:
+            return lr
+        lr *= shrink
+    return lr

@@ -1,0 +1,106 @@
+"""GPU tests of the optimisation layer: Ram-Lak kernel and dose error against
+the oracle's numpy definitions, autograd through the hand-written adjoint
+against the oracle's gradient, and a short plain-initialised optimisation."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import ramlak
+import synth
+from synth.configs import scaled
+
+torch = pytest.importorskip("torch")
+import paper_2211_03516_amd as vam
+from paper_2211_03516_amd import optim
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def relL2(x, ref):
+    x = np.asarray(x, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    return float(np.linalg.norm(x - ref) / max(np.linalg.norm(ref), 1e-300))
+
+
+def test_ramlak_kernel_matches_definition():
+    rng = synth.SplitMix64(31)
+    for nu in (1, 7, 64, 257):
+        rows = rng.uniform(5 * nu).reshape(5, nu) - 0.3
+        say("ramlak nu", nu)
+        for clip in (True, False):
+            got = vam.ramlak_filter(torch.from_numpy(rows).float().to(DEV), pitch=0.8,
+                                    clip_negative=clip).cpu().numpy()
+            ref = ramlak.ramlak_filter(rows, 0.8, clip_negative=clip)
+            assert np.abs(got - ref).max() <= 1e-5 * max(np.abs(ref).max(), 1.0)
+
+
+def test_dose_error_matches_fp64_definition():
+    rng = synth.SplitMix64(32)
+    n = 100003
+    d = rng.uniform(n) * 1.6
+    t = (rng.uniform(n) > 0.6).astype(np.float64)
+    e, rate = vam.dose_error(torch.from_numpy(d).float().to(DEV), torch.from_numpy(t).float().to(DEV), 0.8, 20.0)
+    df = d.astype(np.float32).astype(np.float64)
+    sig = 1.0 / (1.0 + np.exp(-20.0 * (df - np.float32(0.8))))
+    assert e == pytest.approx(np.abs(sig - t).sum() / t.sum(), rel=1e-9)
+    assert rate == pytest.approx(np.mean((df >= np.float32(0.8)) != (t >= 0.5)), abs=1e-12)
+
+
+def _c1_like(n_angles=30):
+    return scaled(synth.workload("c1"), n_angles=n_angles)
+
+
+def test_autograd_dose_gradient_matches_oracle():
+    p = _c1_like()
+    og = oracle.Geometry(p)
+    t, _ = synth.random_config1_target(64, 32.0, seed=5)
+    P0 = oracle.forward(og, t)
+    D0 = oracle.adjoint(og, P0)
+    g0 = P0 / np.percentile(D0[t > 0], 50)
+    _, _, grad_o = oracle.loss_grad(og, t, g0, 20.0, 0.8)
+    g = vam.Geometry(p)
+    gp = torch.from_numpy(g0).float().to(DEV).requires_grad_(True)
+    tt = torch.from_numpy(t).to(DEV)
+    d = optim.dose(gp, g)
+    loss = ((torch.sigmoid(20.0 * (d - 0.8)) - tt) ** 2).mean()
+    loss.backward()
+    e = relL2(gp.grad.double().cpu().numpy(), grad_o)
+    say("autograd gradient rel-L2 vs oracle %.3e" % e)
+    assert e <= 1e-4
+    # Project's backward is the deposit: <A x, y> = <x, A^T y> through autograd
+    x = torch.from_numpy(t).to(DEV).requires_grad_(True)
+    y = torch.rand(g.proj_shape, device=DEV)
+    (optim.project(x, g) * y).sum().backward()
+    ref = g.back(y)
+    assert torch.allclose(x.grad, ref)
+    g.close()
+
+
+def test_plain_init_and_short_optimisation():
+    p = scaled(synth.workload("c5"), n_angles=60)
+    t, _ = synth.random_config2_target(128, p["r_inner"], seed=1)
+    g = vam.Geometry(p)
+    tt = torch.from_numpy(t).to(DEV)
+    g0 = optim.plain_init(tt, g)
+    d0 = g.back(g0)
+    mean_t = float(d0[tt > 0.5].mean())
+    say("plain init: mean target dose %.6f, min proj %.3e" % (mean_t, float(g0.min())))
+    assert mean_t == pytest.approx(1.0, rel=1e-4)
+    assert float(g0.min()) >= 0.0
+    e0, r0 = vam.dose_error(d0, tt)
+    proj, hist = optim.optimize(tt, g, proj=g0.clone(), steps=25)
+    say("dose error %.4f -> %.4f, voxel error %.4f -> %.4f, loss %.5f -> %.5f" % (
+        e0, hist[-1]["dose_error"], r0, hist[-1]["voxel_error"], hist[0]["loss"], hist[-1]["loss"]))
+    assert hist[-1]["loss"] < hist[0]["loss"]
+    assert hist[-1]["dose_error"] < e0
+    assert float(proj.min()) >= 0.0
+    g.close()
