@@ -87,7 +87,11 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--adjoint-variant", type=int, default=0)
     ap.add_argument("--forward-variant", type=int, default=0)
+    ap.add_argument("--box-edge", type=int, default=0)
+    ap.add_argument("--fixed", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0,
+                    help="also run a plain device copy of this many MiB (counter calibration)")
     ap.add_argument("--cpu-threads", type=int, default=0)
     args = ap.parse_args()
 
@@ -114,6 +118,9 @@ def main():
     t_setup = time.perf_counter() - t_setup
     g.set_adjoint_variant(args.adjoint_variant)
     g.set_forward_variant(args.forward_variant)
+    if args.box_edge:
+        g.set_box_edge(args.box_edge)
+    g.set_fixed_kernels(args.fixed)
     rays_hit, samples_per_pass = g.stats()
     vol = torch.from_numpy(target).to(dev)
     proj = torch.empty(g.proj_shape, device=dev)
@@ -122,6 +129,16 @@ def main():
     def step():
         g.forward(vol, out=proj)
         g.back(proj, out=dose)
+
+    if args.copy_calibration:
+        # a plain copy kernel of known size: reads and writes exactly n bytes,
+        # so its FETCH_SIZE / WRITE_SIZE readings scale the counters to bytes
+        n = args.copy_calibration << 20
+        src = torch.ones(n // 4, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     for _ in range(args.warmup):
         step()
@@ -164,7 +181,7 @@ def main():
         "data": "synthetic (seeded union of spheres/boxes/tori, seed %d)" % args.seed,
         "config": {"workload": WORKLOAD_NAME, "samples_per_pass": samples_per_pass,
                    "rays_hit": rays_hit, "adjoint_variant": args.adjoint_variant,
-                   "forward_variant": args.forward_variant},
+                   "forward_variant": args.forward_variant, "box_edge": args.box_edge},
         "roofline": roofline,
         "kernels_ms": {"forward": f_avg, "deposit": b_avg},
         "gather_model": {"bytes_per_sample": GATHER_BYTES_PER_SAMPLE, "kernel": dom,

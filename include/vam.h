@@ -197,8 +197,16 @@ vam_status vam_export_rays(vam_geometry_t h, double* out);
  *                   aggregation (FP32 atomics), 3 = as 2 with an FP64
  *                   accumulator, 4 = tuned scatter (FP32 atomics),
  *                   5 = tuned scatter with an FP64 accumulator,
- *                   6 = lab-box tiled, LDS accumulation, FP64 accumulator,
- *                   7 = lab-box tiled, LDS accumulation, FP32 accumulator.
+ *                   6 = lab-box tiled with FP64 LDS accumulation,
+ *                   7 = lab-box tiled with FP32 LDS accumulation,
+ *                   8 = as 6 with in-register run aggregation.
+ *   op 2, tiling:   variant = lab-box edge in voxels, from 4 up to the
+ *                   largest edge whose FP64 footprint fits in the 160 KiB
+ *                   of LDS (19 for grids of 24^3 voxels and more); rebuilds
+ *                   the box decomposition (synchronises the device).
+ *   op 3, kernels:  1 (default) = use the box kernels specialised to a
+ *                   compile-time footprint for edges 8, 12 and 16,
+ *                   0 = always use the runtime-stride box kernels.
  * FP64 accumulators are allocated on first use.  Errors:
  * VAM_ERR_BAD_HANDLE, VAM_ERR_INVALID_ARG for an unknown op or variant. */
 vam_status vam_set_variant(vam_geometry_t h, int32_t op, int32_t variant);

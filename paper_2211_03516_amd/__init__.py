@@ -31,7 +31,8 @@ OP_FORWARD, OP_DEPOSIT = 0, 1
 FWD_DEFAULT, FWD_PLAIN, FWD_BOX, FWD_TUNED = 0, 1, 2, 3
 ADJ_DEFAULT, ADJ_SCATTER_DIRECT, ADJ_SCATTER_AGGREGATED, ADJ_SCATTER_FP64 = 0, 1, 2, 3
 ADJ_TUNED_FP32, ADJ_TUNED_FP64 = 4, 5
-ADJ_BOX_FP64, ADJ_BOX_FP32 = 6, 7
+ADJ_BOX_FP64, ADJ_BOX_FP32, ADJ_BOX_AGG = 6, 7, 8
+OP_BOX_EDGE, OP_FIXED_KERNELS = 2, 3
 
 
 class VamError(RuntimeError):
@@ -231,6 +232,13 @@ class Geometry:
 
     def set_forward_variant(self, variant):
         _check(lib().vam_set_variant(self.handle, OP_FORWARD, int(variant)))
+
+    def set_fixed_kernels(self, on):
+        _check(lib().vam_set_variant(self.handle, OP_FIXED_KERNELS, int(bool(on))))
+
+    def set_box_edge(self, edge):
+        """Rebuild the lab-box decomposition with boxes of `edge` voxels."""
+        _check(lib().vam_set_variant(self.handle, OP_BOX_EDGE, int(edge)))
 
     def forward(self, vol, out=None, angle_begin=0, angle_count=None, out_dtype=None, stream=None):
         """Projections [angle_count, nv, nu] of vol [nz, ny, nx]."""

@@ -456,7 +456,7 @@ static bool v2_eligible(const vam_geometry* h) {
 
 // Kernels used when the caller asks for the default (fastest measured).
 constexpr int kDefaultForwardVariant = 2;
-constexpr int kDefaultBackVariant = 6;
+constexpr int kDefaultBackVariant = 8;
 
 static inline unsigned blocks_for(int64_t n, int threads) { return (unsigned)((n + threads - 1) / threads); }
 
@@ -529,7 +529,7 @@ vam_status launch_back(vam_geometry* h, const void* proj, vam_dtype proj_t, floa
   const vam_geometry_desc& D = h->desc;
   int variant = h->adjoint_variant == 0 ? kDefaultBackVariant : h->adjoint_variant;
   if ((variant == 4 || variant == 5) && !v2_eligible(h)) variant -= 2;
-  const bool wide = variant == 3 || variant == 5 || variant == 6;
+  const bool wide = variant == 3 || variant == 5 || variant >= 6;
   if (wide && !h->dose_pad64)
     VAM_HIP_TRY(hipMalloc(&h->dose_pad64, h->pad_voxels * sizeof(double)), "allocating the FP64 accumulator");
   if (wide)
@@ -543,7 +543,7 @@ vam_status launch_back(vam_geometry* h, const void* proj, vam_dtype proj_t, floa
   dim3 grid((D.n_u + 63) / 64, (D.n_v + 3) / 4, na), block(64, 4);
   VAM_HIP_TRY(hipEventRecord(h->ev[2], s), "recording an event");
   if (variant >= 6) {
-    launch_box_deposit(h, P, proj, proj_t, na, wide, s);
+    launch_box_deposit(h, P, proj, proj_t, na, variant, s);
   } else {
     switch (proj_t) {
       case VAM_F32: launch_back_t(h, variant, (const float*)proj, P, grid, block, s); break;

@@ -352,6 +352,7 @@ vam_status vam_setup_geometry(const vam_geometry_desc* desc, hipStream_t stream,
   h->magic = kMagic;
   h->desc = *desc;
   h->adjoint_variant = 0;
+  h->fixed_kernels = 1;
   h->angles.resize(desc->n_angles);
   for (int a = 0; a < desc->n_angles; ++a)
     h->angles[a] = desc->angles_rad ? desc->angles_rad[a] : 2.0 * M_PI * a / desc->n_angles;
@@ -476,8 +477,21 @@ vam_status vam_set_variant(vam_geometry_t h, int32_t op, int32_t variant) {
     if (variant < 0 || variant > 3) return fail(VAM_ERR_INVALID_ARG, "unknown forward variant %d", variant);
     h->forward_variant = variant;
   } else if (op == 1) {
-    if (variant < 0 || variant > 7) return fail(VAM_ERR_INVALID_ARG, "unknown deposit variant %d", variant);
+    if (variant < 0 || variant > 8) return fail(VAM_ERR_INVALID_ARG, "unknown deposit variant %d", variant);
     h->adjoint_variant = variant;
+  } else if (op == 3) {
+    if (variant < 0 || variant > 1) return fail(VAM_ERR_INVALID_ARG, "fixed-footprint switch must be 0 or 1");
+    h->fixed_kernels = variant;
+  } else if (op == 2) {
+    const int emax = max_box_edge(h);
+    if (variant < 4 || variant > emax)
+      return fail(VAM_ERR_INVALID_ARG, "box edge %d outside [4, %d] (the FP64 footprint must fit in LDS)", variant,
+                  emax);
+    VAM_HIP_TRY(hipSetDevice(h->device), "hipSetDevice");
+    VAM_HIP_TRY(hipDeviceSynchronize(), "synchronising before rebuilding boxes");
+    free_boxes(h);
+    h->box_edge = variant;
+    return build_boxes(h, nullptr);
   } else {
     return fail(VAM_ERR_INVALID_ARG, "unknown operator %d", op);
   }

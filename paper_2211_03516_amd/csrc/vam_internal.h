@@ -93,6 +93,8 @@ struct vam_geometry {
   hipEvent_t ev[4];
   int ev_valid[2];
   // lab-box segment decomposition
+  int box_edge;                  // box edge in voxels (0: library default)
+  int fixed_kernels;             // 1: use the fixed-footprint box kernels where available
   vam::BoxGrid boxes;
   int n_boxes;                   // boxes holding at least one segment
   int64_t n_segments;
@@ -131,7 +133,9 @@ vam_status build_boxes(vam_geometry* h, hipStream_t s);
 vam_status launch_box_forward(vam_geometry* h, const MarchParams& P, void* proj, vam_dtype proj_t, int na,
                               hipStream_t s);
 void launch_box_deposit(vam_geometry* h, const MarchParams& P, const void* proj, vam_dtype proj_t, int na,
-                        bool wide, hipStream_t s);
+                        int variant, hipStream_t s);
+void free_boxes(vam_geometry* h);
+int max_box_edge(const vam_geometry* h);
 
 }  // namespace vam
 

@@ -213,6 +213,32 @@ def test_forward_variants_agree():
     g.close()
 
 
+def test_box_edges_agree():
+    p = c2_small(48, n_pupil=4, n_angles=6)
+    g = gpu_geom(p)
+    rng = synth.SplitMix64(12)
+    x = to_dev(rng.uniform(48 ** 3).reshape(48, 48, 48))
+    y = to_dev(rng.uniform(6 * 48 * 48).reshape(6, 48, 48))
+    og = oracle.Geometry(p)
+    Pref = oracle.forward(og, x.double().cpu().numpy())
+    Dref = oracle.adjoint(og, y.double().cpu().numpy())
+    for edge in (4, 7, 8, 12, 19, 16):
+        g.set_box_edge(edge)
+        for fixed in (0, 1):
+            g.set_fixed_kernels(fixed)
+            for dep in (vam.ADJ_BOX_FP64, vam.ADJ_BOX_AGG):
+                g.set_adjoint_variant(dep)
+                ef = relL2(g.forward(x).cpu().numpy(), Pref)
+                ea = relL2(g.back(y).cpu().numpy(), Dref)
+                say("box edge %d fixed %d deposit %d: forward %.3e deposit %.3e" % (edge, fixed, dep, ef, ea))
+                assert ef <= 1e-5 and ea <= 1e-5
+    g.set_adjoint_variant(vam.ADJ_DEFAULT)
+    # an edge whose footprint cannot fit in LDS is rejected on the host
+    with pytest.raises(vam.VamError):
+        g.set_box_edge(20)
+    g.close()
+
+
 def test_adjoint_variants_agree():
     p = c2_small(48, n_pupil=4, n_angles=12)
     g = gpu_geom(p)
@@ -221,7 +247,7 @@ def test_adjoint_variants_agree():
     ref = oracle.adjoint(oracle.Geometry(p), y.cpu().numpy().astype(np.float64))
     for variant in (vam.ADJ_SCATTER_DIRECT, vam.ADJ_SCATTER_AGGREGATED, vam.ADJ_SCATTER_FP64,
                     vam.ADJ_TUNED_FP32, vam.ADJ_TUNED_FP64, vam.ADJ_BOX_FP64, vam.ADJ_BOX_FP32,
-                    vam.ADJ_DEFAULT):
+                    vam.ADJ_BOX_AGG, vam.ADJ_DEFAULT):
         g.set_adjoint_variant(variant)
         say("adjoint variant", variant)
         assert relL2(g.back(y).cpu().numpy(), ref) <= 1e-5
@@ -307,7 +333,8 @@ def test_c2_full_adjoint_identity(c2_full):
     lhs = float((Ax * y.double()).sum())
     scale = float(Ax.norm() * y.double().norm())
     res = {}
-    for variant in (vam.ADJ_DEFAULT, vam.ADJ_BOX_FP32, vam.ADJ_TUNED_FP64, vam.ADJ_SCATTER_AGGREGATED):
+    for variant in (vam.ADJ_DEFAULT, vam.ADJ_BOX_AGG, vam.ADJ_BOX_FP32, vam.ADJ_TUNED_FP64,
+                    vam.ADJ_SCATTER_AGGREGATED):
         g.set_adjoint_variant(variant)
         Aty = g.back(y).double()
         rhs = float((x.double() * Aty).sum())
@@ -317,7 +344,9 @@ def test_c2_full_adjoint_identity(c2_full):
     g.set_adjoint_variant(vam.ADJ_DEFAULT)
     # FP64 accumulation: only the FP32 weights round; FP32 atomics add a
     # bias that grows with the ~1e5 deposits per voxel
-    assert res[vam.ADJ_DEFAULT] <= 1e-7 and res[vam.ADJ_TUNED_FP64] <= 1e-7
+    # the FP32 forward sums (~7000 terms per pixel) bound the agreement
+    assert res[vam.ADJ_DEFAULT] <= 5e-7 and res[vam.ADJ_TUNED_FP64] <= 5e-7
+    assert res[vam.ADJ_BOX_AGG] <= 5e-7
     assert max(res.values()) <= 5e-5
 
 
