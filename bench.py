@@ -36,7 +36,7 @@ WORKLOAD_NAME = ("c2: 256^3 FP32 target, 360 angles, 256x256 DMD, thin-lens proj
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("project.hip", "vam_internal.h"):
+    for f in ("project.hip", "boxes.hip", "vam_internal.h"):
         h.update(open(os.path.join(ROOT, "paper_2211_03516_amd", "csrc", f), "rb").read())
     return h.hexdigest()
 
@@ -89,6 +89,9 @@ def main():
     ap.add_argument("--forward-variant", type=int, default=0)
     ap.add_argument("--box-edge", type=int, default=0)
     ap.add_argument("--fixed", type=int, default=1)
+    ap.add_argument("--seg-order", type=int, default=-1)
+    ap.add_argument("--deposit-threads", type=int, default=0)
+    ap.add_argument("--work-order", type=int, default=-1, help="bit 0 forward, bit 1 deposit: XCD-aware")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
@@ -121,6 +124,12 @@ def main():
     if args.box_edge:
         g.set_box_edge(args.box_edge)
     g.set_fixed_kernels(args.fixed)
+    if args.seg_order >= 0:
+        g.set_segment_order(args.seg_order)
+    if args.deposit_threads:
+        g.set_deposit_threads(args.deposit_threads)
+    if args.work_order >= 0:
+        g.set_work_order(args.work_order & 1, args.work_order >> 1)
     rays_hit, samples_per_pass = g.stats()
     vol = torch.from_numpy(target).to(dev)
     proj = torch.empty(g.proj_shape, device=dev)

@@ -207,6 +207,16 @@ vam_status vam_export_rays(vam_geometry_t h, double* out);
  *   op 3, kernels:  1 (default) = use the box kernels specialised to a
  *                   compile-time footprint for edges 8, 12 and 16,
  *                   0 = always use the runtime-stride box kernels.
+ *   op 4, order:    order of the segments inside a box for the deposit:
+ *                   0 = by ray, 1 = by decreasing length, 2 = by pixel
+ *                   parity class then ray (default); rebuilds the boxes.
+ *   op 5, threads:  workgroup size of the fixed-footprint deposit, 256 or
+ *                   512 (default).
+ *   op 6, order:    work order of the box kernels, bit 0 forward, bit 1
+ *                   deposit: 0 = boxes fastest (all XCDs work on the same
+ *                   angles), 1 = XCD-aware (each XCD walks a contiguous
+ *                   range of boxes, angles fastest).  Default 0.
+ *   op 7, order:    as op 4, for the forward projection (default 0).
  * FP64 accumulators are allocated on first use.  Errors:
  * VAM_ERR_BAD_HANDLE, VAM_ERR_INVALID_ARG for an unknown op or variant. */
 vam_status vam_set_variant(vam_geometry_t h, int32_t op, int32_t variant);

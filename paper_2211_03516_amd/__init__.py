@@ -32,7 +32,8 @@ FWD_DEFAULT, FWD_PLAIN, FWD_BOX, FWD_TUNED = 0, 1, 2, 3
 ADJ_DEFAULT, ADJ_SCATTER_DIRECT, ADJ_SCATTER_AGGREGATED, ADJ_SCATTER_FP64 = 0, 1, 2, 3
 ADJ_TUNED_FP32, ADJ_TUNED_FP64 = 4, 5
 ADJ_BOX_FP64, ADJ_BOX_FP32, ADJ_BOX_AGG = 6, 7, 8
-OP_BOX_EDGE, OP_FIXED_KERNELS = 2, 3
+OP_BOX_EDGE, OP_FIXED_KERNELS, OP_SEG_ORDER, OP_DEPOSIT_THREADS, OP_WORK_ORDER = 2, 3, 4, 5, 6
+OP_SEG_ORDER_FWD = 7
 
 
 class VamError(RuntimeError):
@@ -235,6 +236,17 @@ class Geometry:
 
     def set_fixed_kernels(self, on):
         _check(lib().vam_set_variant(self.handle, OP_FIXED_KERNELS, int(bool(on))))
+
+    def set_segment_order(self, order, forward=False):
+        """Rebuild the box decomposition with segment order 0 (ray),
+        1 (length) or 2 (pixel parity class) for the deposit (or forward)."""
+        _check(lib().vam_set_variant(self.handle, OP_SEG_ORDER_FWD if forward else OP_SEG_ORDER, int(order)))
+
+    def set_work_order(self, xcd_forward, xcd_deposit):
+        _check(lib().vam_set_variant(self.handle, OP_WORK_ORDER, int(bool(xcd_forward)) | (int(bool(xcd_deposit)) << 1)))
+
+    def set_deposit_threads(self, n):
+        _check(lib().vam_set_variant(self.handle, OP_DEPOSIT_THREADS, int(n)))
 
     def set_box_edge(self, edge):
         """Rebuild the lab-box decomposition with boxes of `edge` voxels."""

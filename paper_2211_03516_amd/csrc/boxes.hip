@@ -95,10 +95,11 @@ __global__ void k_seg_fill(BoxGrid G, const RayRec* rays, const double* ray64, i
 }
 
 void free_boxes(vam_geometry* h) {
-  void* ptrs[] = {h->segs, h->box_begin, h->box_id, h->ray_nseg, h->seg_part};
+  void* ptrs[] = {h->segs, h->segs_fwd, h->box_begin, h->box_id, h->ray_nseg, h->seg_part};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   h->segs = nullptr;
+  h->segs_fwd = nullptr;
   h->box_begin = nullptr;
   h->box_id = nullptr;
   h->ray_nseg = nullptr;
@@ -110,6 +111,8 @@ void free_boxes(vam_geometry* h) {
 
 struct BoxParams {
   BoxGrid G;
+  int nboxes, na;      // work items of the launch: boxes x angles
+  int xcd;             // 1: XCD-aware work order (see work_item)
   const int4* segs;
   const int* box_begin;
   const int* box_id;
@@ -196,16 +199,36 @@ vam_status build_boxes(vam_geometry* h, hipStream_t s) {
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   release();
   if (e != hipSuccess) return hip_check(e, "filling box segments");
-  // Order each box's segments by ray: neighbouring lanes then handle
-  // neighbouring pixels (coalesced projection accesses), and the order no
-  // longer depends on the scheduling of the fill kernel.
+  // Order each box's segments, once for the deposit (h->segs) and once for
+  // the forward projection (h->segs_fwd); sorting also makes the order
+  // independent of the scheduling of the fill kernel:
+  //  0: by ray -- neighbouring lanes handle neighbouring pixels;
+  //  1: by decreasing length -- lanes of a wave march similar lengths;
+  //  2: by pixel parity class (u mod 2, v mod 2), then ray -- the lanes of
+  //     a wave handle pixels two apart, whose trilinear stencils are disjoint.
   {
     std::vector<int4> hs(std::max<int64_t>(total, 1));
     e = hipMemcpy(hs.data(), h->segs, total * sizeof(int4), hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_check(e, "reading box segments");
-    for (size_t i = 0; i + 1 < begin.size(); ++i)
-      std::sort(hs.begin() + begin[i], hs.begin() + begin[i + 1],
-                [](const int4& x, const int4& y) { return x.x < y.x; });
+    const int nu = D.n_u, nv = D.n_v;
+    auto sort_by = [&](int order) {
+      auto key = [&](const int4& s) -> int64_t {
+        const int r = s.x;
+        const int u = r % nu, v = (r / nu) % nv;
+        if (order == 1) return ((int64_t)(0x7fff - s.z) << 32) | (uint32_t)r;
+        if (order == 2) return ((int64_t)(((v & 1) << 1) | (u & 1)) << 32) | (uint32_t)r;
+        return r;
+      };
+      for (size_t i = 0; i + 1 < begin.size(); ++i)
+        std::sort(hs.begin() + begin[i], hs.begin() + begin[i + 1],
+                  [&](const int4& x, const int4& y) { return key(x) < key(y); });
+    };
+    e = hipMalloc(&h->segs_fwd, std::max<int64_t>(total, 1) * sizeof(int4));
+    if (e != hipSuccess) return hip_check(e, "allocating forward segments");
+    sort_by(h->seg_order_fwd);
+    e = hipMemcpy(h->segs_fwd, hs.data(), total * sizeof(int4), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_check(e, "writing forward segments");
+    sort_by(h->seg_order);
     e = hipMemcpy(h->segs, hs.data(), total * sizeof(int4), hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_check(e, "writing box segments");
     std::vector<int> ns(h->n_rays);
@@ -247,6 +270,40 @@ __device__ inline void store_proj(uint16_t* p, int64_t i, float x) {
   }
 }
 __device__ inline void store_proj(__half* p, int64_t i, float x) { p[i] = __float2half_rn(x); }
+
+
+// XCD-aware work order.  Workgroups of a launch are handed to the 8 XCDs
+// round-robin (workgroup L runs on XCD L mod 8), each XCD with its own L2.
+// Work item w = (box, angle) is numbered box-major, angle-minor; XCD x takes
+// the contiguous range [x per, (x + 1) per) in order.  The workgroups in
+// flight on one XCD then share one or two boxes at neighbouring angles, so
+// the box's segment and ray records and its volume footprint are fetched
+// from HBM once and reused from that XCD's L2.
+constexpr int kXcds = 8;
+
+__device__ inline bool work_item(int nboxes, int na, int xcd, int& b, int& a) {
+  if (!xcd) {  // natural order: boxes fastest, all XCDs on the same angles
+    const int64_t L = blockIdx.x;
+    if (L >= (int64_t)nboxes * na) return false;
+    a = (int)(L / nboxes);
+    b = (int)(L - (int64_t)a * nboxes);
+    return true;
+  }
+  const int64_t W = (int64_t)nboxes * na;
+  const int64_t per = (W + kXcds - 1) / kXcds;
+  const int64_t L = blockIdx.x;
+  const int64_t i = L / kXcds;
+  const int64_t w = (L % kXcds) * per + i;
+  if (i >= per || w >= W) return false;
+  b = (int)(w / na);
+  a = (int)(w - (int64_t)b * na);
+  return true;
+}
+
+static inline dim3 work_grid(int nboxes, int na, int xcd) {
+  const int64_t W = (int64_t)nboxes * na;
+  return dim3((unsigned)(xcd ? ((W + kXcds - 1) / kXcds) * kXcds : W));
+}
 
 // Rotated-box footprint [X0, X1) x [Y0, Y1) x [Z0, Z1) in padded grid cells.
 struct Foot {
@@ -290,8 +347,8 @@ __global__ __launch_bounds__(256) void k_back_box(MarchParams P, BoxParams Bp, c
                                                   double* __restrict__ dose) {
   extern __shared__ __align__(16) unsigned char smem[];
   LT* acc = reinterpret_cast<LT*>(smem);
-  const int b = blockIdx.x;
-  const int a = blockIdx.y;
+  int b, a;
+  if (!work_item(Bp.nboxes, Bp.na, Bp.xcd, b, a)) return;
   const int box = Bp.box_id[b];
   const double2 cs = P.cs[P.a0 + a];
   const Foot f = footprint(Bp, box, cs.x, cs.y, P.cx, P.cy);
@@ -443,8 +500,8 @@ __global__ __launch_bounds__(256) void k_forward_boxc(MarchParams P, BoxParams B
                                                       float* __restrict__ part, int64_t n_rays, int smax) {
   constexpr int SY = Fixed<B>::WXY, SZ = SY * SY, NC = SZ * Fixed<B>::WZ;
   __shared__ float sv[NC];
-  const int b = blockIdx.x;
-  const int a = blockIdx.y;
+  int b, a;
+  if (!work_item(Bp.nboxes, Bp.na, Bp.xcd, b, a)) return;
   const double2 cs = P.cs[P.a0 + a];
   const Foot f = footprint(Bp, Bp.box_id[b], cs.x, cs.y, P.cx, P.cy);
   for (int i = threadIdx.x; i < NC; i += blockDim.x) {
@@ -487,13 +544,13 @@ __global__ __launch_bounds__(256) void k_forward_boxc(MarchParams P, BoxParams B
   }
 }
 
-template <int B, typename PT, bool AGG>
-__global__ __launch_bounds__(256) void k_back_boxc(MarchParams P, BoxParams Bp, const PT* __restrict__ proj,
-                                                   double* __restrict__ dose) {
+template <int B, typename PT, bool AGG, int NT>
+__global__ __launch_bounds__(NT) void k_back_boxc(MarchParams P, BoxParams Bp, const PT* __restrict__ proj,
+                                                  double* __restrict__ dose) {
   constexpr int SY = Fixed<B>::WXY, SZ = SY * SY, NC = SZ * Fixed<B>::WZ;
   __shared__ double acc[NC];
-  const int b = blockIdx.x;
-  const int a = blockIdx.y;
+  int b, a;
+  if (!work_item(Bp.nboxes, Bp.na, Bp.xcd, b, a)) return;
   const double2 cs = P.cs[P.a0 + a];
   const Foot f = footprint(Bp, Bp.box_id[b], cs.x, cs.y, P.cx, P.cy);
   for (int i = threadIdx.x; i < NC; i += blockDim.x) acc[i] = 0.0;
@@ -586,6 +643,9 @@ static bool fixed_edge(int B) { return B == 8 || B == 12 || B == 16; }
 BoxParams box_params(const vam_geometry* h) {
   BoxParams Bp;
   Bp.G = h->boxes;
+  Bp.nboxes = h->n_boxes;
+  Bp.na = 0;
+  Bp.xcd = 0;
   Bp.segs = h->segs;
   Bp.box_begin = h->box_begin;
   Bp.box_id = h->box_id;
@@ -608,15 +668,26 @@ static void launch_box_k(vam_geometry* h, const MarchParams& P, const BoxParams&
                               kMaxLdsBytes);
     configured |= 1 << bit;
   }
-  hipLaunchKernelGGL((k_back_box<PT, LT, AGG>), dim3(h->n_boxes, na), dim3(256), lds, s, P, Bp, proj,
+  BoxParams Bw = Bp;
+  Bw.nboxes = h->n_boxes;
+  Bw.na = na;
+  Bw.xcd = h->xcd_deposit;
+  hipLaunchKernelGGL((k_back_box<PT, LT, AGG>), work_grid(h->n_boxes, na, Bw.xcd), dim3(256), lds, s, P, Bw, proj,
                      h->dose_pad64);
 }
 
 template <int B, typename PT, bool AGG>
 static void launch_boxc(vam_geometry* h, const MarchParams& P, const BoxParams& Bp, const PT* proj, int na,
                         hipStream_t s) {
-  hipLaunchKernelGGL((k_back_boxc<B, PT, AGG>), dim3(h->n_boxes, na), dim3(256), 0, s, P, Bp, proj,
-                     h->dose_pad64);
+  BoxParams Bw = Bp;
+  Bw.nboxes = h->n_boxes;
+  Bw.na = na;
+  Bw.xcd = h->xcd_deposit;
+  const dim3 grid = work_grid(h->n_boxes, na, Bw.xcd);
+  if (h->deposit_threads == 512)
+    hipLaunchKernelGGL((k_back_boxc<B, PT, AGG, 512>), grid, dim3(512), 0, s, P, Bw, proj, h->dose_pad64);
+  else
+    hipLaunchKernelGGL((k_back_boxc<B, PT, AGG, 256>), grid, dim3(256), 0, s, P, Bw, proj, h->dose_pad64);
 }
 
 template <typename PT>
@@ -665,8 +736,8 @@ template <typename AT>
 __global__ __launch_bounds__(256) void k_forward_box(MarchParams P, BoxParams Bp, const float* __restrict__ vol,
                                                      float* __restrict__ part, int64_t n_rays, int smax) {
   extern __shared__ float sv[];
-  const int b = blockIdx.x;
-  const int a = blockIdx.y;
+  int b, a;
+  if (!work_item(Bp.nboxes, Bp.na, Bp.xcd, b, a)) return;
   const int box = Bp.box_id[b];
   const double2 cs = P.cs[P.a0 + a];
   const Foot f = footprint(Bp, box, cs.x, cs.y, P.cx, P.cy);
@@ -752,12 +823,17 @@ static vam_status forward_box_t(vam_geometry* h, const MarchParams& P0, PT* proj
     const int nc = std::min(h->seg_part_angles, na - c0);
     MarchParams P = P0;
     P.a0 = P0.a0 + c0;
+    BoxParams Bw = Bp;
+    Bw.nboxes = h->n_boxes;
+    Bw.na = nc;
+    Bw.xcd = h->xcd_forward;
+    Bw.segs = h->segs_fwd;
     if (h->n_boxes > 0 && fixed_edge(h->boxes.B) && h->fixed_kernels) {
-      const dim3 grid(h->n_boxes, nc);
+      const dim3 grid = work_grid(h->n_boxes, nc, Bw.xcd);
       switch (h->boxes.B) {
-        case 8: hipLaunchKernelGGL(k_forward_boxc<8>, grid, dim3(256), 0, s, P, Bp, h->vol_pad, h->seg_part, h->n_rays, smax); break;
-        case 12: hipLaunchKernelGGL(k_forward_boxc<12>, grid, dim3(256), 0, s, P, Bp, h->vol_pad, h->seg_part, h->n_rays, smax); break;
-        default: hipLaunchKernelGGL(k_forward_boxc<16>, grid, dim3(256), 0, s, P, Bp, h->vol_pad, h->seg_part, h->n_rays, smax); break;
+        case 8: hipLaunchKernelGGL(k_forward_boxc<8>, grid, dim3(256), 0, s, P, Bw, h->vol_pad, h->seg_part, h->n_rays, smax); break;
+        case 12: hipLaunchKernelGGL(k_forward_boxc<12>, grid, dim3(256), 0, s, P, Bw, h->vol_pad, h->seg_part, h->n_rays, smax); break;
+        default: hipLaunchKernelGGL(k_forward_boxc<16>, grid, dim3(256), 0, s, P, Bw, h->vol_pad, h->seg_part, h->n_rays, smax); break;
       }
     } else if (h->n_boxes > 0) {
       static thread_local bool configured = false;
@@ -766,7 +842,7 @@ static vam_status forward_box_t(vam_geometry* h, const MarchParams& P0, PT* proj
                                   kMaxLdsBytes);
         configured = true;
       }
-      hipLaunchKernelGGL((k_forward_box<float>), dim3(h->n_boxes, nc), dim3(256), lds, s, P, Bp, h->vol_pad,
+      hipLaunchKernelGGL((k_forward_box<float>), work_grid(h->n_boxes, nc, Bw.xcd), dim3(256), lds, s, P, Bw, h->vol_pad,
                          h->seg_part, h->n_rays, smax);
     }
     const int64_t n = (int64_t)nc * npix;

@@ -321,7 +321,7 @@ static void free_handle(vam_geometry* h) {
   for (int i = 0; i < 4; ++i)
     if (h->ev[i]) (void)hipEventDestroy(h->ev[i]);
   void* ptrs[] = {h->rays, h->ray64, h->angle_cs, h->vol_pad, h->dose_pad, h->dose_pad64,
-                  h->segs, h->box_begin, h->box_id, h->ray_nseg, h->seg_part,
+                  h->segs, h->segs_fwd, h->box_begin, h->box_id, h->ray_nseg, h->seg_part,
                   h->resid, h->grad, h->dose_tmp, h->loss_part};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
@@ -353,6 +353,8 @@ vam_status vam_setup_geometry(const vam_geometry_desc* desc, hipStream_t stream,
   h->desc = *desc;
   h->adjoint_variant = 0;
   h->fixed_kernels = 1;
+  h->seg_order = 2;
+  h->deposit_threads = 512;
   h->angles.resize(desc->n_angles);
   for (int a = 0; a < desc->n_angles; ++a)
     h->angles[a] = desc->angles_rad ? desc->angles_rad[a] : 2.0 * M_PI * a / desc->n_angles;
@@ -479,6 +481,20 @@ vam_status vam_set_variant(vam_geometry_t h, int32_t op, int32_t variant) {
   } else if (op == 1) {
     if (variant < 0 || variant > 8) return fail(VAM_ERR_INVALID_ARG, "unknown deposit variant %d", variant);
     h->adjoint_variant = variant;
+  } else if (op == 4 || op == 7) {
+    if (variant < 0 || variant > 2) return fail(VAM_ERR_INVALID_ARG, "segment order must be 0, 1 or 2");
+    VAM_HIP_TRY(hipSetDevice(h->device), "hipSetDevice");
+    VAM_HIP_TRY(hipDeviceSynchronize(), "synchronising before rebuilding boxes");
+    free_boxes(h);
+    (op == 4 ? h->seg_order : h->seg_order_fwd) = variant;
+    return build_boxes(h, nullptr);
+  } else if (op == 5) {
+    if (variant != 256 && variant != 512) return fail(VAM_ERR_INVALID_ARG, "deposit workgroup size must be 256 or 512");
+    h->deposit_threads = variant;
+  } else if (op == 6) {
+    if (variant < 0 || variant > 3) return fail(VAM_ERR_INVALID_ARG, "work order flags must be in [0, 3]");
+    h->xcd_forward = variant & 1;
+    h->xcd_deposit = (variant >> 1) & 1;
   } else if (op == 3) {
     if (variant < 0 || variant > 1) return fail(VAM_ERR_INVALID_ARG, "fixed-footprint switch must be 0 or 1");
     h->fixed_kernels = variant;

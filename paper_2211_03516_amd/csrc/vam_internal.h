@@ -95,10 +95,15 @@ struct vam_geometry {
   // lab-box segment decomposition
   int box_edge;                  // box edge in voxels (0: library default)
   int fixed_kernels;             // 1: use the fixed-footprint box kernels where available
+  int seg_order;                 // deposit order of segments inside a box (see build_boxes)
+  int seg_order_fwd;             // forward order of segments inside a box
+  int deposit_threads;           // workgroup size of the fixed-footprint deposit (256 or 512)
+  int xcd_forward, xcd_deposit;  // 1: XCD-aware work order for the box kernels
   vam::BoxGrid boxes;
   int n_boxes;                   // boxes holding at least one segment
   int64_t n_segments;
-  int4* segs;                    // [n_segments], grouped by box, by ray within a box
+  int4* segs;                    // [n_segments], grouped by box, deposit order within a box
+  int4* segs_fwd;                // the same segments in the forward projection's order
   int* ray_nseg;                 // [n_rays] segments per ray
   int max_seg_per_ray;
   float* seg_part;               // forward partial sums [angles][rank][ray], on first use
