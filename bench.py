@@ -29,9 +29,18 @@ GATHER_BYTES_PER_SAMPLE = 32
 PEAK_FP32_VECTOR_TFLOPS = 157.3
 PEAK_HBM_GBPS = 8000.0
 
-WORKLOAD_NAME = ("c2: 256^3 FP32 target, 360 angles, 256x256 DMD, thin-lens projector "
-                 "(10 deg edge chief ray), 16 pupil samples (12.2 deg), refracting vial "
-                 "R_o 120 / R_i 112, n 1/1.47/1.49, alpha 0.005/voxel, step 0.5")
+WORKLOAD_NAMES = {
+    "c2": ("c2: 256^3 target, 360 angles, 256x256 DMD, thin-lens projector "
+           "(10 deg edge chief ray), 16 pupil samples (12.2 deg), refracting vial "
+           "R_o 120 / R_i 112, n 1/1.47/1.49, alpha 0.005/voxel, step 0.5"),
+    "c4": ("c4: 512^3 target, 360 angles, 512x512 DMD, thin-lens projector "
+           "(15 deg edge chief ray), 8 pupil samples (12.2 deg), refracting vial "
+           "R_o 240 / R_i 224, n 1/1.47/1.49, alpha 0.005/voxel, step 0.5"),
+    "c5": ("c5: 128^3 target, 180 angles, 128x128 DMD, thin-lens projector "
+           "(10 deg edge chief ray), 8 pupil samples, vial R_o 60 / R_i 56"),
+    "c1": ("c1: 64^3 target, 90 angles, 64x64 DMD, telecentric chief rays, "
+           "index-matched vial R 32, alpha 0.01/voxel"),
+}
 
 
 def kernel_source_hash():
@@ -62,19 +71,19 @@ def cpu_baseline(p, target, threads):
     import numpy as np
     import oracle
     og = oracle.Geometry(p)
-    angles = [0, 180]
+    angles = [0, p["n_angles"] // 2]
     n_samples = 0
     t0 = time.perf_counter()
-    P = oracle.forward(og, target, a0=0, na=1, nthreads=threads)
-    P2 = oracle.forward(og, target, a0=180, na=1, nthreads=threads)
-    oracle.adjoint(og, P, a0=0, na=1, nthreads=threads)
-    oracle.adjoint(og, P2, a0=180, na=1, nthreads=threads)
+    P = oracle.forward(og, target, a0=angles[0], na=1, nthreads=threads)
+    P2 = oracle.forward(og, target, a0=angles[1], na=1, nthreads=threads)
+    oracle.adjoint(og, P, a0=angles[0], na=1, nthreads=threads)
+    oracle.adjoint(og, P2, a0=angles[1], na=1, nthreads=threads)
     dt = time.perf_counter() - t0
     for a in angles:
         n_samples += 2 * oracle.count_samples(og, a0=a, na=1, nthreads=threads)
     return {
         "value": n_samples / dt, "unit": "samples/s", "cores": threads, "kind": "oracle",
-        "sample": "forward + dose deposit of angles 0 and 180 of the same workload "
+        "sample": "forward + dose deposit of angles %d and %d of the same workload " % tuple(angles) +
                   "(%d samples, %.1f s wall, FP64 C++ std::thread)" % (n_samples, dt),
     }
 
@@ -82,6 +91,9 @@ def cpu_baseline(p, target, threads):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOAD_NAMES))
+    ap.add_argument("--dtype", default="f32", choices=["f32", "bf16", "f16"],
+                    help="storage type of the volume and projections (accumulation is FP32/FP64)")
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--seed", type=int, default=0)
@@ -113,8 +125,12 @@ def main():
         print("bench.py needs a HIP device", file=sys.stderr)
         sys.exit(1)
     dev = torch.device("cuda:0")
-    p = synth.workload("c2")
-    target, _ = synth.random_config2_target(p["nx"], p["r_inner"], seed=args.seed)
+    p = synth.workload(args.workload)
+    if args.workload == "c1":
+        target, _ = synth.random_config1_target(p["nx"], p["r_inner"], seed=args.seed)
+    else:
+        target, _ = synth.random_config2_target(p["nx"], p["r_inner"], seed=args.seed)
+    tdt = {"f32": torch.float32, "bf16": torch.bfloat16, "f16": torch.float16}[args.dtype]
     t_setup = time.perf_counter()
     g = vam.Geometry(p)
     torch.cuda.synchronize()
@@ -131,13 +147,24 @@ def main():
     if args.work_order >= 0:
         g.set_work_order(args.work_order & 1, args.work_order >> 1)
     rays_hit, samples_per_pass = g.stats()
-    vol = torch.from_numpy(target).to(dev)
-    proj = torch.empty(g.proj_shape, device=dev)
+    vol = torch.from_numpy(target).to(dev, dtype=tdt)
+    proj = torch.empty(g.proj_shape, device=dev, dtype=tdt)
     dose = torch.empty(g.vol_shape, device=dev)
+
+    # The deposit skips rays whose projection value is 0 (their contribution
+    # is exactly zero), so its speed depends on how much of each projection
+    # is empty.  The headline step deposits a dense input -- the target's
+    # projections plus a floor of 1e-3 of their maximum, computed once -- so
+    # that every counted sample is processed; the target's own projections
+    # (empty outside its shadow) are timed separately as `deposit_sparse_ms`.
+    g.forward(vol, out=proj)
+    dense = proj.float() + float(proj.float().max()) * 1e-3
+    dense = dense.to(tdt)
+    torch.cuda.synchronize()
 
     def step():
         g.forward(vol, out=proj)
-        g.back(proj, out=dose)
+        g.back(dense, out=dose)
 
     if args.copy_calibration:
         # a plain copy kernel of known size: reads and writes exactly n bytes,
@@ -160,7 +187,8 @@ def main():
     t0 = time.perf_counter()
     for _ in range(args.steps):
         step()
-        # kernel events are read after the timed region
+        # the library's per-kernel events are read after each step (one
+        # synchronisation per ~0.6 s step)
         torch.cuda.synchronize()
         f, b = g.kernel_times()
         fwd_ms.append(f)
@@ -173,10 +201,18 @@ def main():
     value = 2.0 * samples_per_pass * args.steps / (total_ms * 1e-3)
 
     f_avg, b_avg = float(np.mean(fwd_ms)), float(np.mean(back_ms))
+    # deposit of the target's own projections (zero outside its shadow)
+    g.forward(vol, out=proj)
+    sparse_ms = []
+    for _ in range(max(1, args.steps)):
+        g.back(proj, out=dose)
+        torch.cuda.synchronize()
+        sparse_ms.append(g.kernel_times()[1])
+    active = float((proj != 0).float().mean())
     dom, dom_ms = ("deposit", b_avg) if b_avg >= f_avg else ("forward", f_avg)
     flop = FLOP_PER_SAMPLE * samples_per_pass
     achieved = flop / (dom_ms * 1e-3) / 1e12
-    traffic = load_traffic(dom)
+    traffic = load_traffic(dom) if (args.workload, args.dtype) == ("c2", "f32") else None
     roofline = {
         "bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
         "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": traffic,
@@ -186,13 +222,14 @@ def main():
     out = {
         "metric": "ray-voxel samples/s fwd+adj", "value": value, "unit": "samples/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": args.dtype,
         "data": "synthetic (seeded union of spheres/boxes/tori, seed %d)" % args.seed,
-        "config": {"workload": WORKLOAD_NAME, "samples_per_pass": samples_per_pass,
+        "config": {"workload": WORKLOAD_NAMES[args.workload], "samples_per_pass": samples_per_pass,
                    "rays_hit": rays_hit, "adjoint_variant": args.adjoint_variant,
                    "forward_variant": args.forward_variant, "box_edge": args.box_edge},
         "roofline": roofline,
-        "kernels_ms": {"forward": f_avg, "deposit": b_avg},
+        "kernels_ms": {"forward": f_avg, "deposit": b_avg, "deposit_sparse_ms": float(np.mean(sparse_ms)),
+                       "sparse_nonzero_pixel_fraction": active},
         "gather_model": {"bytes_per_sample": GATHER_BYTES_PER_SAMPLE, "kernel": dom,
                          "GBps": gather_gbps, "frac_of_hbm_peak": gather_gbps / PEAK_HBM_GBPS},
         "setup_s": t_setup, "wall_s": wall,

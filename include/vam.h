@@ -173,6 +173,15 @@ vam_status vam_ramlak_filter(const float* proj_in, float* proj_out, int32_t n_ro
 vam_status vam_dose_error(const float* dose, const float* target, int64_t n, double threshold,
                           double sharpness, double* out2, hipStream_t stream);
 
+/* 8-bit export of projections (Sec. 2.7): over all n FP32 values (device),
+ * mean and population standard deviation in FP64; clip = mean + 3 std;
+ * out[i] = round-half-even(255 * min(max(proj[i], 0), clip) / clip), the
+ * product formed in FP64 (0 everywhere if clip <= 0).  out: n bytes
+ * (device).  stats3 (host, optional): mean, std, clip; passing it
+ * synchronises `stream`. */
+vam_status vam_equalize_u8(const float* proj, int64_t n, uint8_t* out, double* stats3,
+                           hipStream_t stream);
+
 /* Ray-table statistics: rays that reach the resin, and ray-voxel samples
  * over all angles whose anti-aliasing stencil touches the grid (one pass of
  * vam_forward_project or vam_back_project over all angles processes this

@@ -93,6 +93,7 @@ def lib():
             "vam_kernel_times": [_P, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)],
             "vam_ramlak_filter": [_P, _P, _I32, _I32, ctypes.c_double, _I32, _P],
             "vam_dose_error": [_P, _P, ctypes.c_int64, ctypes.c_double, ctypes.c_double, _DP, _P],
+            "vam_equalize_u8": [_P, ctypes.c_int64, _P, _DP, _P],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -326,6 +327,17 @@ def dose_error(dose, target, threshold=0.8, sharpness=20.0, stream=None):
     _check(lib().vam_dose_error(dose.data_ptr(), target.data_ptr(), dose.numel(), float(threshold),
                                 float(sharpness), ctypes.cast(out, _DP), _stream_ptr(stream)))
     return out[0], out[1]
+
+
+def equalize_u8(proj, stream=None):
+    """8-bit export of projections: (uint8 tensor, (mean, std, clip))."""
+    torch = _torch()
+    _need_device_tensor(proj, "proj", None, (torch.float32,))
+    out = torch.empty(proj.shape, dtype=torch.uint8, device=proj.device)
+    st = (ctypes.c_double * 3)()
+    _check(lib().vam_equalize_u8(proj.data_ptr(), proj.numel(), out.data_ptr(), ctypes.cast(st, _DP),
+                                 _stream_ptr(stream)))
+    return out, (st[0], st[1], st[2])
 
 
 def version():

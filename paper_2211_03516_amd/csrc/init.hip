@@ -11,6 +11,8 @@
 // scaled by tau so that a unit-pitch discrete convolution approximates the
 // continuous filter, followed by clipping at zero.
 //
+// Export: see k_eq_map below.
+//
 // Dose error: the termination test of Sec. 2.7 compares simulated and target
 // dose; here E = ||sigmoid(kappa (d - thr)) - t||_1 / ||t||_1 together with
 // the fraction of voxels whose thresholded dose (d >= thr) differs from the
@@ -97,6 +99,68 @@ __global__ void k_dose_error_final(const double* __restrict__ part, int nblocks,
   }
 }
 
+// Projection export (Sec. 2.7): values above mean + 3 std over all pixels of
+// all angles are clipped, then the range [0, clip] is rescaled to 8 bits.
+// Statistics in FP64; the scaled value v = x * (255 / clip) is formed in FP64
+// and rounded to nearest even.
+constexpr int kEqThreads = 256;
+constexpr int kEqBlocks = 1024;
+
+__global__ __launch_bounds__(kEqThreads) void k_eq_stats(const float* __restrict__ p, int64_t n,
+                                                         double* __restrict__ part) {
+  __shared__ double red[2][kEqThreads / 64];
+  double s1 = 0.0, s2 = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const double x = p[i];
+    s1 += x;
+    s2 += x * x;
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    s1 += __shfl_down(s1, off, 64);
+    s2 += __shfl_down(s2, off, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    red[0][threadIdx.x >> 6] = s1;
+    red[1][threadIdx.x >> 6] = s2;
+  }
+  __syncthreads();
+  if (threadIdx.x < 2) {
+    double s = 0.0;
+    for (int w = 0; w < kEqThreads / 64; ++w) s += red[threadIdx.x][w];
+    part[2 * blockIdx.x + threadIdx.x] = s;
+  }
+}
+
+// stats[0] mean, stats[1] population std, stats[2] clip = mean + 3 std
+__global__ void k_eq_final(const double* __restrict__ part, int nblocks, int64_t n, double* __restrict__ stats) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    double s1 = 0.0, s2 = 0.0;
+    for (int b = 0; b < nblocks; ++b) {
+      s1 += part[2 * b];
+      s2 += part[2 * b + 1];
+    }
+    const double mean = s1 / (double)n;
+    const double var = fmax(s2 / (double)n - mean * mean, 0.0);
+    const double sd = sqrt(var);
+    stats[0] = mean;
+    stats[1] = sd;
+    stats[2] = mean + 3.0 * sd;
+  }
+}
+
+__global__ void k_eq_map(const float* __restrict__ p, int64_t n, const double* __restrict__ stats,
+                         uint8_t* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double clip = stats[2];
+  double v = 0.0;
+  if (clip > 0.0) {
+    const double x = fmin(fmax((double)p[i], 0.0), clip);
+    v = rint(x * (255.0 / clip));
+  }
+  out[i] = (uint8_t)fmin(fmax(v, 0.0), 255.0);
+}
+
 }  // namespace vam
 
 using namespace vam;
@@ -137,6 +201,25 @@ vam_status vam_dose_error(const float* dose, const float* target, int64_t n, dou
   if (e == hipSuccess) e = hipStreamSynchronize(stream);
   (void)hipFreeAsync(part, stream);
   if (e != hipSuccess) return hip_check(e, "dose error");
+  return VAM_OK;
+}
+
+vam_status vam_equalize_u8(const float* proj, int64_t n, uint8_t* out, double* stats3, hipStream_t stream) {
+  clear_error();
+  if (!proj || !out) return fail(VAM_ERR_INVALID_ARG, "NULL buffer");
+  if (n < 1) return fail(VAM_ERR_INVALID_ARG, "n must be >= 1");
+  double* part = nullptr;
+  const int blocks = (int)std::min<int64_t>(kEqBlocks, (n + kEqThreads - 1) / kEqThreads);
+  VAM_HIP_TRY(hipMallocAsync((void**)&part, (2 * blocks + 3) * sizeof(double), stream), "allocating partials");
+  double* st = part + 2 * blocks;
+  hipLaunchKernelGGL(k_eq_stats, dim3(blocks), dim3(kEqThreads), 0, stream, proj, n, part);
+  hipLaunchKernelGGL(k_eq_final, dim3(1), dim3(64), 0, stream, part, blocks, n, st);
+  hipLaunchKernelGGL(k_eq_map, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, proj, n, st, out);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess && stats3) e = hipMemcpyAsync(stats3, st, 3 * sizeof(double), hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess && stats3) e = hipStreamSynchronize(stream);
+  (void)hipFreeAsync(part, stream);
+  if (e != hipSuccess) return hip_check(e, "equalisation");
   return VAM_OK;
 }
 

@@ -45,12 +45,33 @@ def _inside(prim, z, y, x):
     raise ValueError(kind)
 
 
+def _extent(p):
+    """Radius of a sphere around the centre that holds the primitive."""
+    k = p["kind"]
+    if k == "zcyl":
+        return float(np.hypot(p["r"], p["h"]))
+    if k == "gauss":
+        return np.inf
+    return _bounding_radius(p)
+
+
 def primitive_target(shape, prims):
-    """Union of primitives voxelised at voxel centres, float32 {0,1}."""
+    """Union of primitives voxelised at voxel centres, float32 {0,1}.  Each
+    primitive is evaluated on the sub-grid of its bounding box only."""
+    nz, ny, nx = shape
     z, y, x = _centres(shape)
     out = np.zeros(shape, dtype=bool)
     for p in prims:
-        out |= np.broadcast_to(_inside(p, z, y, x), shape)
+        r = _extent(p) + 1.0
+        c = p["centre"]
+        sl = []
+        for ax, (n, ci) in enumerate(((nz, c[2]), (ny, c[1]), (nx, c[0]))):
+            lo = max(int(np.floor(ci - r + (n - 1) / 2.0)), 0)
+            hi = min(int(np.ceil(ci + r + (n - 1) / 2.0)) + 1, n)
+            sl.append(slice(lo, max(lo, hi)))
+        zs, ys, xs = z[sl[0]], y[:, sl[1]], x[:, :, sl[2]]
+        sub = out[sl[0], sl[1], sl[2]]
+        sub |= np.broadcast_to(_inside(p, zs, ys, xs), sub.shape)
     return out.astype(np.float32)
 
 
@@ -150,12 +171,13 @@ def random_config3_target(n, r_inner, seed):
 def fin_stack_target(n, voxel_mm, fins=9, thickness_mm=1.0, period_mm=2.25,
                      width_mm=8.0, base_mm=2.0):
     """Stack of `fins` parallel plates normal to the vial axis (thickness and
-    period as printed in the paper's results section), on a square base,
-    centred on the axis with the base at the grid centre plane."""
+    period as printed in the paper's results section) on a square base,
+    joined by a central spine, centred on the axis and in z."""
     z, y, x = _centres((n, n, n))
     half_w = 0.5 * width_mm / voxel_mm
     in_xy = (np.abs(x) <= half_w) & (np.abs(y) <= half_w)
-    zz = z * voxel_mm
+    height = base_mm + fins * period_mm
+    zz = z * voxel_mm + 0.5 * height - base_mm   # base occupies [-base_mm, 0)
     base = (zz >= -base_mm) & (zz < 0)
     fin = np.zeros_like(zz, dtype=bool)
     for f in range(fins):

@@ -104,3 +104,24 @@ def test_plain_init_and_short_optimisation():
     assert hist[-1]["dose_error"] < e0
     assert float(proj.min()) >= 0.0
     g.close()
+
+
+def test_equalize_u8_matches_definition():
+    from oracle import export
+    rng = synth.SplitMix64(41)
+    x = (rng.uniform(360 * 64 * 64) ** 3 * 5.0).reshape(360, 64, 64)
+    x[0, 0, :8] = -1.0
+    xt = torch.from_numpy(x).float().to(DEV)
+    q, st = vam.equalize_u8(xt)
+    xf = x.astype(np.float32).astype(np.float64)   # the values as stored
+    ref, (mean, sd, clip) = export.equalize_u8(xf)
+    assert st[0] == pytest.approx(mean, rel=1e-12)
+    assert st[1] == pytest.approx(sd, rel=1e-10)
+    got = q.cpu().numpy()
+    # a level is unique unless the scaled value sits at a half level within
+    # the rounding of the FP64 statistics
+    v = np.minimum(np.maximum(xf, 0), clip) * (255.0 / clip)
+    ambiguous = np.abs(v - np.floor(v) - 0.5) < 1e-9
+    assert np.array_equal(got[~ambiguous], ref[~ambiguous])
+    assert np.all(np.abs(got[ambiguous].astype(int) - ref[ambiguous].astype(int)) <= 1)
+    say("equalize: mean %.6f std %.6f clip %.6f, %d ambiguous" % (mean, sd, clip, int(ambiguous.sum())))

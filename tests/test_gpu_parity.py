@@ -378,3 +378,36 @@ def test_optimize_step_matches_oracle_loss_and_gradient():
     say("gradient step rel-L2 %.3e" % e)
     assert e <= 1e-4
     g.close()
+
+
+# ------------------------------------------------- c4: 512^3 precision ----
+
+@pytest.mark.parametrize("dt", ["f32", "bf16", "f16"])
+def test_c4_reduced_precision_64_angles(dt):
+    """512^3, 360 angles, 512^2 DMD, 8 pupil samples: per-projection rel-L2
+    against the FP64 oracle on 64 angles a = floor(k 360 / 64), estimated on
+    64 sampled pixels per angle, for a smooth (non-binary) volume stored in
+    FP32, BF16 or FP16.  Bounds: 1e-5 (FP32), 2u (u = 2^-8, 2^-11)."""
+    p = synth.workload("c4")
+    n = 512
+    t, _ = synth.random_config2_target(n, p["r_inner"], seed=0)
+    blob = synth.gaussian_blob_volume((n, n, n), (20.0, -35.0, 10.0), 60.0).astype(np.float32)
+    vol = 0.6 * t + 0.4 * blob
+    tdt = {"f32": torch.float32, "bf16": torch.bfloat16, "f16": torch.float16}[dt]
+    bound = {"f32": 1e-5, "bf16": 2 * 2.0 ** -8, "f16": 2 * 2.0 ** -11}[dt]
+    g = gpu_geom(p)
+    say("c4 forward", dt)
+    P = g.forward(to_dev(vol, tdt), out_dtype=tdt).float().cpu().numpy()
+    g.close()
+    angles = [int(k * 360 // 64) for k in range(64)]
+    rng = synth.SplitMix64(40)
+    vv = (rng.uniform(64 * 64) * n).astype(np.int32)
+    uu = (rng.uniform(64 * 64) * n).astype(np.int32)
+    ang = np.repeat(angles, 64).astype(np.int32)
+    # the oracle sees the volume as stored
+    vs = torch.from_numpy(vol).to(tdt).float().numpy().astype(np.float64)
+    ref = oracle.forward_pixels(oracle.Geometry(p), vs if dt != "f32" else vol, ang, vv, uu)
+    got = P[ang, vv, uu]
+    per = [relL2(got[i * 64:(i + 1) * 64], ref[i * 64:(i + 1) * 64]) for i in range(64)]
+    say("c4 %s per-projection rel-L2: max %.3e mean %.3e (bound %.3e)" % (dt, max(per), np.mean(per), bound))
+    assert max(per) <= bound
