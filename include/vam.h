@@ -208,7 +208,10 @@ vam_status vam_export_rays(vam_geometry_t h, double* out);
  *                   5 = tuned scatter with an FP64 accumulator,
  *                   6 = lab-box tiled with FP64 LDS accumulation,
  *                   7 = lab-box tiled with FP32 LDS accumulation,
- *                   8 = as 6 with in-register run aggregation.
+ *                   8 = as 6 with in-register run aggregation,
+ *                   9 = voxel-driven gather through an inverse ray map
+ *                   (lab-frame unit cells -> sample runs; built on first
+ *                   use, ~32 bytes per run; no atomics, fixed order).
  *   op 2, tiling:   variant = lab-box edge in voxels, from 4 up to the
  *                   largest edge whose FP64 footprint fits in the 160 KiB
  *                   of LDS (19 for grids of 24^3 voxels and more); rebuilds

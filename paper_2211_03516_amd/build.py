@@ -7,7 +7,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libvam.so")
-SOURCES = ["setup.hip", "project.hip", "boxes.hip", "optimize.hip", "init.hip"]
+SOURCES = ["setup.hip", "project.hip", "boxes.hip", "gather.hip", "optimize.hip", "init.hip", "cnn.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

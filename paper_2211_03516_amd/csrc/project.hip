@@ -528,6 +528,17 @@ vam_status launch_back(vam_geometry* h, const void* proj, vam_dtype proj_t, floa
                        int a0, int na, hipStream_t s) {
   const vam_geometry_desc& D = h->desc;
   int variant = h->adjoint_variant == 0 ? kDefaultBackVariant : h->adjoint_variant;
+  if (variant == 9) {
+    // voxel-driven gather: writes (or adds to) the output directly
+    vam_status st = prepare_gather(h, s);
+    if (st != VAM_OK) return st;
+    VAM_HIP_TRY(hipEventRecord(h->ev[2], s), "recording an event");
+    st = launch_gather_deposit(h, proj, proj_t, dose, accumulate, a0, na, s);
+    if (st != VAM_OK) return st;
+    VAM_HIP_TRY(hipEventRecord(h->ev[3], s), "recording an event");
+    h->ev_valid[1] = 1;
+    return VAM_OK;
+  }
   if ((variant == 4 || variant == 5) && !v2_eligible(h)) variant -= 2;
   const bool wide = variant == 3 || variant == 5 || variant >= 6;
   if (wide && !h->dose_pad64)

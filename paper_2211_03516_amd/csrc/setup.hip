@@ -322,7 +322,7 @@ static void free_handle(vam_geometry* h) {
     if (h->ev[i]) (void)hipEventDestroy(h->ev[i]);
   void* ptrs[] = {h->rays, h->ray64, h->angle_cs, h->vol_pad, h->dose_pad, h->dose_pad64,
                   h->segs, h->segs_fwd, h->box_begin, h->box_id, h->ray_nseg, h->seg_part,
-                  h->resid, h->grad, h->dose_tmp, h->loss_part};
+                  h->resid, h->grad, h->dose_tmp, h->loss_part, h->cell_begin, h->gseg};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   h->magic = 0;
@@ -479,7 +479,7 @@ vam_status vam_set_variant(vam_geometry_t h, int32_t op, int32_t variant) {
     if (variant < 0 || variant > 3) return fail(VAM_ERR_INVALID_ARG, "unknown forward variant %d", variant);
     h->forward_variant = variant;
   } else if (op == 1) {
-    if (variant < 0 || variant > 8) return fail(VAM_ERR_INVALID_ARG, "unknown deposit variant %d", variant);
+    if (variant < 0 || variant > 9) return fail(VAM_ERR_INVALID_ARG, "unknown deposit variant %d", variant);
     h->adjoint_variant = variant;
   } else if (op == 4 || op == 7) {
     if (variant < 0 || variant > 2) return fail(VAM_ERR_INVALID_ARG, "segment order must be 0, 1 or 2");

@@ -111,6 +111,11 @@ struct vam_geometry {
   int* box_begin;                // [n_boxes + 1] segment offsets
   int* box_id;                   // [n_boxes] linear box index (x fastest)
   int box_cells;                 // largest rotated-box footprint in cells (LDS)
+  // inverse ray map of the voxel-driven gather deposit, built on first use
+  vam::BoxGrid cells;            // lab-frame unit cells
+  int* cell_begin;               // [cells + 1] entry offsets
+  float4* gseg;                  // [n_gseg][2] cell entries
+  int64_t n_gseg;
   // statistics
   int64_t rays_hit;
   int64_t samples_per_pass;
@@ -141,6 +146,12 @@ void launch_box_deposit(vam_geometry* h, const MarchParams& P, const void* proj,
                         int variant, hipStream_t s);
 void free_boxes(vam_geometry* h);
 int max_box_edge(const vam_geometry* h);
+// voxel-driven gather deposit through the inverse ray map (gather.hip);
+// prepare_gather builds the map on first use (synchronises the stream)
+vam_status prepare_gather(vam_geometry* h, hipStream_t s);
+vam_status launch_gather_deposit(vam_geometry* h, const void* proj, vam_dtype proj_t, float* dose,
+                                 int accumulate, int a0, int na, hipStream_t s);
+void free_gather(vam_geometry* h);
 
 }  // namespace vam
 

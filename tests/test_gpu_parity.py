@@ -247,10 +247,41 @@ def test_adjoint_variants_agree():
     ref = oracle.adjoint(oracle.Geometry(p), y.cpu().numpy().astype(np.float64))
     for variant in (vam.ADJ_SCATTER_DIRECT, vam.ADJ_SCATTER_AGGREGATED, vam.ADJ_SCATTER_FP64,
                     vam.ADJ_TUNED_FP32, vam.ADJ_TUNED_FP64, vam.ADJ_BOX_FP64, vam.ADJ_BOX_FP32,
-                    vam.ADJ_BOX_AGG, vam.ADJ_DEFAULT):
+                    vam.ADJ_BOX_AGG, vam.ADJ_GATHER, vam.ADJ_DEFAULT):
         g.set_adjoint_variant(variant)
         say("adjoint variant", variant)
         assert relL2(g.back(y).cpu().numpy(), ref) <= 1e-5
+    g.close()
+
+
+def test_gather_deposit_angles_accumulate_and_order():
+    # the voxel-driven gather against the oracle on an angle sub-range, with
+    # accumulation into an existing dose, and bitwise repeatable
+    p = c2_small(40, n_pupil=6, n_angles=10)
+    g = gpu_geom(p)
+    g.set_adjoint_variant(vam.ADJ_GATHER)
+    rng = synth.SplitMix64(13)
+    y = rng.uniform(10 * 40 * 40).reshape(10, 40, 40)
+    og = oracle.Geometry(p)
+    ref = oracle.adjoint(og, y[3:8], a0=3, na=5)
+    D1 = g.back(to_dev(y[3:8]), angle_begin=3)
+    D2 = g.back(to_dev(y[3:8]), angle_begin=3)
+    assert torch.equal(D1, D2)
+    say("gather sub-range rel-L2 %.3e" % relL2(D1.cpu().numpy(), ref))
+    assert relL2(D1.cpu().numpy(), ref) <= 1e-5
+    base = to_dev(rng.uniform(40 ** 3).reshape(40, 40, 40))
+    acc = base.clone()
+    g.back(to_dev(y[3:8]), angle_begin=3, out=acc, accumulate=True)
+    assert relL2((acc - base).cpu().numpy(), ref) <= 1e-5
+    # telecentric, index-matched rays (c1 optics)
+    p1 = scaled(synth.workload("c1"), n_angles=20)
+    g1 = gpu_geom(p1)
+    g1.set_adjoint_variant(vam.ADJ_GATHER)
+    y1 = rng.uniform(20 * 64 * 64).reshape(20, 64, 64)
+    e1 = relL2(g1.back(to_dev(y1)).cpu().numpy(), oracle.adjoint(oracle.Geometry(p1), y1))
+    say("gather c1 rel-L2 %.3e" % e1)
+    assert e1 <= 1e-5
+    g1.close()
     g.close()
 
 
@@ -308,7 +339,7 @@ def test_c2_full_adjoint_one_angle(c2_full):
     rng = synth.SplitMix64(22)
     y = rng.uniform(256 * 256).reshape(1, 256, 256)
     ref = oracle.adjoint(oracle.Geometry(p), y, a0=37, na=1)
-    for variant in (vam.ADJ_DEFAULT, vam.ADJ_TUNED_FP64):
+    for variant in (vam.ADJ_DEFAULT, vam.ADJ_TUNED_FP64, vam.ADJ_GATHER):
         g.set_adjoint_variant(variant)
         say("c2 full adjoint, angle 37, variant", variant)
         D = g.back(to_dev(y), angle_begin=37).cpu().numpy()
@@ -334,7 +365,7 @@ def test_c2_full_adjoint_identity(c2_full):
     scale = float(Ax.norm() * y.double().norm())
     res = {}
     for variant in (vam.ADJ_DEFAULT, vam.ADJ_BOX_AGG, vam.ADJ_BOX_FP32, vam.ADJ_TUNED_FP64,
-                    vam.ADJ_SCATTER_AGGREGATED):
+                    vam.ADJ_SCATTER_AGGREGATED, vam.ADJ_GATHER):
         g.set_adjoint_variant(variant)
         Aty = g.back(y).double()
         rhs = float((x.double() * Aty).sum())
@@ -346,7 +377,7 @@ def test_c2_full_adjoint_identity(c2_full):
     # bias that grows with the ~1e5 deposits per voxel
     # the FP32 forward sums (~7000 terms per pixel) bound the agreement
     assert res[vam.ADJ_DEFAULT] <= 5e-7 and res[vam.ADJ_TUNED_FP64] <= 5e-7
-    assert res[vam.ADJ_BOX_AGG] <= 5e-7
+    assert res[vam.ADJ_BOX_AGG] <= 5e-7 and res[vam.ADJ_GATHER] <= 5e-7
     assert max(res.values()) <= 5e-5
 
 
