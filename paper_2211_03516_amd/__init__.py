@@ -18,7 +18,8 @@ import numpy as np
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libvam.so")
-HEADER = os.path.join(os.path.dirname(PKG), "include", "vam.h")
+INCLUDE = os.path.join(os.path.dirname(PKG), "include")
+HEADER = os.path.join(INCLUDE, "vam.h")
 
 VAM_OK, VAM_ERR_INVALID_ARG, VAM_ERR_UNSUPPORTED = 0, -1, -2
 VAM_ERR_OUT_OF_MEMORY, VAM_ERR_HIP, VAM_ERR_BAD_HANDLE = -3, -4, -5
@@ -95,6 +96,14 @@ def lib():
             "vam_ramlak_filter": [_P, _P, _I32, _I32, ctypes.c_double, _I32, _P],
             "vam_dose_error": [_P, _P, ctypes.c_int64, ctypes.c_double, ctypes.c_double, _DP, _P],
             "vam_equalize_u8": [_P, ctypes.c_int64, _P, _DP, _P],
+            "vam_cnn_create": [_I32, _I32, _I32, _I32, _I32, ctypes.c_float, ctypes.c_float, ctypes.POINTER(_P)],
+            "vam_cnn_destroy": [_P],
+            "vam_cnn_set_params": [_P, _P],
+            "vam_cnn_get_params": [_P, _P],
+            "vam_cnn_get_grads": [_P, _P],
+            "vam_cnn_forward": [_P, _P, _I32, _P, _P],
+            "vam_cnn_loss_grad": [_P, _P, _P, _I32, _DP, _P],
+            "vam_cnn_adam_step": [_P, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, _P],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -104,15 +113,20 @@ def lib():
         L.vam_last_error.argtypes = []
         L.vam_version.restype = ctypes.c_int32
         L.vam_version.argtypes = []
+        L.vam_cnn_param_count.restype = ctypes.c_int64
+        L.vam_cnn_param_count.argtypes = [_P]
         _lib = L
     return _lib
 
 
 def header_functions():
-    """Names of the functions include/vam.h declares."""
-    text = open(HEADER).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(vam_[a-z0-9_]+)\s*\(", text)))
+    """Names of the functions the headers under include/ declare."""
+    names = set()
+    for f in sorted(os.listdir(INCLUDE)):
+        if f.endswith(".h"):
+            text = re.sub(r"/\*.*?\*/", "", open(os.path.join(INCLUDE, f)).read(), flags=re.S)
+            names.update(re.findall(r"\b(vam_[a-z0-9_]+)\s*\(", text))
+    return sorted(names)
 
 
 def _check(status):
@@ -343,3 +357,77 @@ def equalize_u8(proj, stream=None):
 
 def version():
     return lib().vam_version()
+
+
+class Cnn:
+    """Learned-initialiser network (include/vam_cnn.h): `layers` 3x3
+    convolutions, `channels` hidden channels, H x W images, residual on the
+    second input image.  Parameters are a flat FP32 numpy array in the
+    library's layout (per layer W[c_out][3][3][c_in], then b[c_out])."""
+
+    def __init__(self, layers=6, channels=64, height=128, width=128, max_batch=16, in_scale=(1.0, 1.0)):
+        h = _P()
+        _check(lib().vam_cnn_create(layers, channels, height, width, max_batch, float(in_scale[0]),
+                                    float(in_scale[1]), ctypes.byref(h)))
+        self.handle = h
+        self.layers, self.channels, self.height, self.width = layers, channels, height, width
+        self.max_batch = max_batch
+        self.in_scale = (float(in_scale[0]), float(in_scale[1]))
+        self.n_params = int(lib().vam_cnn_param_count(h))
+
+    def close(self):
+        if self.handle:
+            lib().vam_cnn_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, params):
+        a = np.ascontiguousarray(params, dtype=np.float32)
+        if a.size != self.n_params:
+            raise ValueError("expected %d parameters, got %d" % (self.n_params, a.size))
+        _check(lib().vam_cnn_set_params(self.handle, a.ctypes.data))
+
+    def get_params(self):
+        a = np.empty(self.n_params, dtype=np.float32)
+        _check(lib().vam_cnn_get_params(self.handle, a.ctypes.data))
+        return a
+
+    def grads(self):
+        a = np.empty(self.n_params, dtype=np.float32)
+        _check(lib().vam_cnn_get_grads(self.handle, a.ctypes.data))
+        return a
+
+    def _images(self, x, name, chans):
+        torch = _torch()
+        shape = (x.shape[0], chans, self.height, self.width) if chans else (x.shape[0], self.height, self.width)
+        _need_device_tensor(x, name, shape, (torch.float32,))
+        if not 1 <= x.shape[0] <= self.max_batch:
+            raise ValueError("batch of %d outside [1, %d]" % (x.shape[0], self.max_batch))
+
+    def forward(self, x, out=None, stream=None):
+        """x [n][2][H][W] -> y [n][H][W] (device FP32)."""
+        torch = _torch()
+        self._images(x, "x", 2)
+        if out is None:
+            out = torch.empty((x.shape[0], self.height, self.width), device=x.device, dtype=torch.float32)
+        self._images(out, "out", 0)
+        _check(lib().vam_cnn_forward(self.handle, x.data_ptr(), x.shape[0], out.data_ptr(), _stream_ptr(stream)))
+        return out
+
+    def loss_grad(self, x, t, want_loss=True, stream=None):
+        """Loss (scaled squared error) and gradients for one batch."""
+        self._images(x, "x", 2)
+        self._images(t, "t", 0)
+        loss = ctypes.c_double(0.0)
+        _check(lib().vam_cnn_loss_grad(self.handle, x.data_ptr(), t.data_ptr(), x.shape[0],
+                                       ctypes.byref(loss) if want_loss else None, _stream_ptr(stream)))
+        return loss.value if want_loss else None
+
+    def adam_step(self, lr, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+        _check(lib().vam_cnn_adam_step(self.handle, float(lr), float(beta1), float(beta2), float(eps),
+                                       _stream_ptr(stream)))

@@ -14,10 +14,11 @@ from .targets import (
     random_config2_target, random_config3_target, fin_stack_target,
 )
 from .configs import workload, WORKLOADS
+from . import cnninit
 
 __all__ = [
     "SplitMix64", "splitmix64_outputs", "pupil_concentric_jittered",
     "pupil_hex13", "concentric_map", "primitive_target",
     "gaussian_blob_volume", "random_config1_target", "random_config2_target",
-    "random_config3_target", "fin_stack_target", "workload", "WORKLOADS",
+    "random_config3_target", "fin_stack_target", "workload", "WORKLOADS", "cnninit",
 ]
