@@ -211,7 +211,10 @@ vam_status vam_export_rays(vam_geometry_t h, double* out);
  *                   8 = as 6 with in-register run aggregation,
  *                   9 = voxel-driven gather through an inverse ray map
  *                   (lab-frame unit cells -> sample runs; built on first
- *                   use, ~32 bytes per run; no atomics, fixed order).
+ *                   use, ~32 bytes per run; no atomics, fixed order),
+ *                   10 = as 8, but consecutive cells share the corners of
+ *                   their common face in registers (four LDS adds per cell
+ *                   crossed instead of eight).
  *   op 2, tiling:   variant = lab-box edge in voxels, from 4 up to the
  *                   largest edge whose FP64 footprint fits in the 160 KiB
  *                   of LDS (19 for grids of 24^3 voxels and more); rebuilds

@@ -544,7 +544,7 @@ __global__ __launch_bounds__(256) void k_forward_boxc(MarchParams P, BoxParams B
   }
 }
 
-template <int B, typename PT, bool AGG, int NT>
+template <int B, typename PT, int AGG, int NT>
 __global__ __launch_bounds__(NT) void k_back_boxc(MarchParams P, BoxParams Bp, const PT* __restrict__ proj,
                                                   double* __restrict__ dose) {
   constexpr int SY = Fixed<B>::WXY, SZ = SY * SY, NC = SZ * Fixed<B>::WZ;
@@ -569,6 +569,7 @@ __global__ __launch_bounds__(NT) void k_back_boxc(MarchParams P, BoxParams Bp, c
     float kf = 0.0f;
     unsigned cur = 0xffffffffu;
     float w[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int cx = -1, cy = 0, cz = 0;  // AGG == 2: cell whose corners w holds
     for (int k = 0; k < cnt; ++k, kf += 1.0f) {
       const float x = __builtin_amdgcn_fmed3f(fmaf(kf, g.dx, g.px), 0.0f, hx);
       const float y = __builtin_amdgcn_fmed3f(fmaf(kf, g.dy, g.py), 0.0f, hy);
@@ -581,7 +582,87 @@ __global__ __launch_bounds__(NT) void k_back_boxc(MarchParams P, BoxParams Bp, c
       const float y11 = z1 * fy, y10 = z1 - y11;
       const float q[8] = {y00 - y00 * fx, y00 * fx, y01 - y01 * fx, y01 * fx,
                           y10 - y10 * fx, y10 * fx, y11 - y11 * fx, y11 * fx};
-      if (AGG) {
+      if (AGG == 2) {
+        // Corner sharing: moving one cell along an axis keeps the four
+        // corners on the far face, so only the four on the near face are
+        // added to LDS; the kept sums shift to the near side and the far
+        // side restarts at zero.  Steps of more than one cell (Delta s > 1)
+        // flush all eight corners.
+        const int ix = (int)x, iy = (int)y, iz = (int)z;
+        const int ex = ix - cx, ey = iy - cy, ez = iz - cz;
+        if (cx >= 0 && (ex < -1 || ex > 1 || ey < -1 || ey > 1 || ez < -1 || ez > 1)) {
+          double* p = acc + (__umul24((unsigned)cz, SZ) + __umul24((unsigned)cy, SY) + (unsigned)cx);
+          atomicAdd(p, (double)w[0]);
+          atomicAdd(p + 1, (double)w[1]);
+          atomicAdd(p + SY, (double)w[2]);
+          atomicAdd(p + SY + 1, (double)w[3]);
+          atomicAdd(p + SZ, (double)w[4]);
+          atomicAdd(p + SZ + 1, (double)w[5]);
+          atomicAdd(p + SZ + SY, (double)w[6]);
+          atomicAdd(p + SZ + SY + 1, (double)w[7]);
+#pragma unroll
+          for (int c = 0; c < 8; ++c) w[c] = 0.0f;
+          cx = -1;
+        }
+        if (cx < 0) {
+          cx = ix;
+          cy = iy;
+          cz = iz;
+        } else {
+          unsigned base = __umul24((unsigned)cz, SZ) + __umul24((unsigned)cy, SY) + (unsigned)cx;
+          if (ex != 0) {
+            const bool up = ex > 0;  // near face: corners with x bit 0 (up) or 1
+            double* p = acc + base + (up ? 0 : 1);
+            atomicAdd(p, (double)(up ? w[0] : w[1]));
+            atomicAdd(p + SY, (double)(up ? w[2] : w[3]));
+            atomicAdd(p + SZ, (double)(up ? w[4] : w[5]));
+            atomicAdd(p + SZ + SY, (double)(up ? w[6] : w[7]));
+#pragma unroll
+            for (int c = 0; c < 8; c += 2) {
+              const float lo = w[c], hi = w[c + 1];
+              w[c] = up ? hi : 0.0f;
+              w[c + 1] = up ? 0.0f : lo;
+            }
+            base += ex;
+            cx = ix;
+          }
+          if (ey != 0) {
+            const bool up = ey > 0;
+            double* p = acc + base + (up ? 0 : SY);
+            atomicAdd(p, (double)(up ? w[0] : w[2]));
+            atomicAdd(p + 1, (double)(up ? w[1] : w[3]));
+            atomicAdd(p + SZ, (double)(up ? w[4] : w[6]));
+            atomicAdd(p + SZ + 1, (double)(up ? w[5] : w[7]));
+            const int pair[4] = {0, 1, 4, 5};
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+              const int c = pair[j];
+              const float lo = w[c], hi = w[c + 2];
+              w[c] = up ? hi : 0.0f;
+              w[c + 2] = up ? 0.0f : lo;
+            }
+            base += ey * SY;
+            cy = iy;
+          }
+          if (ez != 0) {
+            const bool up = ez > 0;
+            double* p = acc + base + (up ? 0 : SZ);
+            atomicAdd(p, (double)(up ? w[0] : w[4]));
+            atomicAdd(p + 1, (double)(up ? w[1] : w[5]));
+            atomicAdd(p + SY, (double)(up ? w[2] : w[6]));
+            atomicAdd(p + SY + 1, (double)(up ? w[3] : w[7]));
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+              const float lo = w[c], hi = w[c + 4];
+              w[c] = up ? hi : 0.0f;
+              w[c + 4] = up ? 0.0f : lo;
+            }
+            cz = iz;
+          }
+        }
+#pragma unroll
+        for (int c = 0; c < 8; ++c) w[c] += q[c];
+      } else if (AGG) {
         if (o != cur) {
           if (cur != 0xffffffffu) {
             double* p = acc + cur;
@@ -614,7 +695,18 @@ __global__ __launch_bounds__(NT) void k_back_boxc(MarchParams P, BoxParams Bp, c
       }
       e = fmaf(e, P.r_hi, e * P.r_lo);
     }
-    if (AGG && cur != 0xffffffffu) {
+    if (AGG == 2 && cx >= 0) {
+      double* p = acc + (__umul24((unsigned)cz, SZ) + __umul24((unsigned)cy, SY) + (unsigned)cx);
+      atomicAdd(p, (double)w[0]);
+      atomicAdd(p + 1, (double)w[1]);
+      atomicAdd(p + SY, (double)w[2]);
+      atomicAdd(p + SY + 1, (double)w[3]);
+      atomicAdd(p + SZ, (double)w[4]);
+      atomicAdd(p + SZ + 1, (double)w[5]);
+      atomicAdd(p + SZ + SY, (double)w[6]);
+      atomicAdd(p + SZ + SY + 1, (double)w[7]);
+    }
+    if (AGG == 1 && cur != 0xffffffffu) {
       double* p = acc + cur;
       atomicAdd(p, (double)w[0]);
       atomicAdd(p + 1, (double)w[1]);
@@ -676,7 +768,7 @@ static void launch_box_k(vam_geometry* h, const MarchParams& P, const BoxParams&
                      h->dose_pad64);
 }
 
-template <int B, typename PT, bool AGG>
+template <int B, typename PT, int AGG>
 static void launch_boxc(vam_geometry* h, const MarchParams& P, const BoxParams& Bp, const PT* proj, int na,
                         hipStream_t s) {
   BoxParams Bw = Bp;
@@ -694,15 +786,22 @@ template <typename PT>
 static void launch_box_t(vam_geometry* h, const MarchParams& P, const PT* proj, int na, int variant,
                          hipStream_t s) {
   const BoxParams Bp = box_params(h);
-  if ((variant == 6 || variant == 8) && fixed_edge(h->boxes.B) && h->fixed_kernels) {
-    const bool agg = variant == 8;
-    switch (h->boxes.B) {
-      case 8: agg ? launch_boxc<8, PT, true>(h, P, Bp, proj, na, s) : launch_boxc<8, PT, false>(h, P, Bp, proj, na, s); break;
-      case 12: agg ? launch_boxc<12, PT, true>(h, P, Bp, proj, na, s) : launch_boxc<12, PT, false>(h, P, Bp, proj, na, s); break;
-      default: agg ? launch_boxc<16, PT, true>(h, P, Bp, proj, na, s) : launch_boxc<16, PT, false>(h, P, Bp, proj, na, s); break;
+  if ((variant == 6 || variant == 8 || variant == 10) && fixed_edge(h->boxes.B) && h->fixed_kernels) {
+    const int agg = variant == 10 ? 2 : variant == 8 ? 1 : 0;
+    switch (h->boxes.B * 4 + agg) {
+      case 8 * 4 + 0: launch_boxc<8, PT, 0>(h, P, Bp, proj, na, s); break;
+      case 8 * 4 + 1: launch_boxc<8, PT, 1>(h, P, Bp, proj, na, s); break;
+      case 8 * 4 + 2: launch_boxc<8, PT, 2>(h, P, Bp, proj, na, s); break;
+      case 12 * 4 + 0: launch_boxc<12, PT, 0>(h, P, Bp, proj, na, s); break;
+      case 12 * 4 + 1: launch_boxc<12, PT, 1>(h, P, Bp, proj, na, s); break;
+      case 12 * 4 + 2: launch_boxc<12, PT, 2>(h, P, Bp, proj, na, s); break;
+      case 16 * 4 + 0: launch_boxc<16, PT, 0>(h, P, Bp, proj, na, s); break;
+      case 16 * 4 + 1: launch_boxc<16, PT, 1>(h, P, Bp, proj, na, s); break;
+      default: launch_boxc<16, PT, 2>(h, P, Bp, proj, na, s); break;
     }
     return;
   }
+  if (variant == 10) variant = 8;  // runtime-stride kernels: cell-run aggregation
   switch (variant) {
     case 7: launch_box_k<PT, float, false>(h, P, Bp, proj, na, s); break;
     case 8: launch_box_k<PT, double, true>(h, P, Bp, proj, na, s); break;

@@ -226,7 +226,7 @@ def test_box_edges_agree():
         g.set_box_edge(edge)
         for fixed in (0, 1):
             g.set_fixed_kernels(fixed)
-            for dep in (vam.ADJ_BOX_FP64, vam.ADJ_BOX_AGG):
+            for dep in (vam.ADJ_BOX_FP64, vam.ADJ_BOX_AGG, vam.ADJ_BOX_SHARED):
                 g.set_adjoint_variant(dep)
                 ef = relL2(g.forward(x).cpu().numpy(), Pref)
                 ea = relL2(g.back(y).cpu().numpy(), Dref)
@@ -247,10 +247,26 @@ def test_adjoint_variants_agree():
     ref = oracle.adjoint(oracle.Geometry(p), y.cpu().numpy().astype(np.float64))
     for variant in (vam.ADJ_SCATTER_DIRECT, vam.ADJ_SCATTER_AGGREGATED, vam.ADJ_SCATTER_FP64,
                     vam.ADJ_TUNED_FP32, vam.ADJ_TUNED_FP64, vam.ADJ_BOX_FP64, vam.ADJ_BOX_FP32,
-                    vam.ADJ_BOX_AGG, vam.ADJ_GATHER, vam.ADJ_DEFAULT):
+                    vam.ADJ_BOX_AGG, vam.ADJ_GATHER, vam.ADJ_BOX_SHARED, vam.ADJ_DEFAULT):
         g.set_adjoint_variant(variant)
         say("adjoint variant", variant)
         assert relL2(g.back(y).cpu().numpy(), ref) <= 1e-5
+    g.close()
+
+
+@pytest.mark.parametrize("step", [0.3, 1.3, 2.2])
+def test_box_deposits_any_step(step):
+    # corner sharing assumes one cell per step; longer steps flush all eight
+    p = c2_small(40, n_pupil=4, n_angles=8, step=step)
+    g = gpu_geom(p)
+    rng = synth.SplitMix64(14)
+    y = rng.uniform(8 * 40 * 40).reshape(8, 40, 40)
+    ref = oracle.adjoint(oracle.Geometry(p), y)
+    for variant in (vam.ADJ_BOX_AGG, vam.ADJ_BOX_SHARED):
+        g.set_adjoint_variant(variant)
+        e = relL2(g.back(to_dev(y)).cpu().numpy(), ref)
+        say("step %.1f deposit %d rel-L2 %.3e" % (step, variant, e))
+        assert e <= 1e-5
     g.close()
 
 
@@ -365,7 +381,7 @@ def test_c2_full_adjoint_identity(c2_full):
     scale = float(Ax.norm() * y.double().norm())
     res = {}
     for variant in (vam.ADJ_DEFAULT, vam.ADJ_BOX_AGG, vam.ADJ_BOX_FP32, vam.ADJ_TUNED_FP64,
-                    vam.ADJ_SCATTER_AGGREGATED, vam.ADJ_GATHER):
+                    vam.ADJ_SCATTER_AGGREGATED, vam.ADJ_GATHER, vam.ADJ_BOX_SHARED):
         g.set_adjoint_variant(variant)
         Aty = g.back(y).double()
         rhs = float((x.double() * Aty).sum())
@@ -377,7 +393,7 @@ def test_c2_full_adjoint_identity(c2_full):
     # bias that grows with the ~1e5 deposits per voxel
     # the FP32 forward sums (~7000 terms per pixel) bound the agreement
     assert res[vam.ADJ_DEFAULT] <= 5e-7 and res[vam.ADJ_TUNED_FP64] <= 5e-7
-    assert res[vam.ADJ_BOX_AGG] <= 5e-7 and res[vam.ADJ_GATHER] <= 5e-7
+    assert res[vam.ADJ_BOX_AGG] <= 5e-7 and res[vam.ADJ_GATHER] <= 5e-7 and res[vam.ADJ_BOX_SHARED] <= 5e-7
     assert max(res.values()) <= 5e-5
 
 
