@@ -66,6 +66,29 @@ def load_traffic(kernel):
     return k.get("fetch_bytes", 0) + k.get("write_bytes", 0)
 
 
+def learned_vs_plain():
+    """Secondary metric (seconds and steps to the plain method's dose error,
+    learned vs plain start) from the committed c5 run of
+    paper_2211_03516_amd.learned; it takes minutes of data generation and
+    training, so it is not re-measured here."""
+    path = os.path.join(ROOT, "profiles", "learned_c5.txt")
+    if not os.path.exists(path):
+        return None
+    cmd, summary = None, None
+    for line in open(path):
+        if line.startswith("# command:"):
+            cmd = line.split(":", 1)[1].strip()
+        elif '"phase": "summary"' in line:
+            summary = json.loads(line)
+    if summary is None:
+        return None
+    return {"metric": "s to target dose error (learned vs plain)", "unit": "s",
+            "learned_s": summary["mean_learned_s"], "plain_s": summary["mean_plain_s"],
+            "learned_steps": summary["mean_learned_steps"], "plain_steps": summary["mean_plain_steps"],
+            "targets": summary["targets"], "workload": "c5: 128^3, 180 angles, 128^2 DMD, 8 pupil samples",
+            "source": "profiles/learned_c5.txt", "command": cmd}
+
+
 def cpu_baseline(p, target, threads):
     """The FP64 oracle on a bounded sample of the same workload."""
     import numpy as np
@@ -104,10 +127,13 @@ def main():
     ap.add_argument("--seg-order", type=int, default=-1)
     ap.add_argument("--deposit-threads", type=int, default=0)
     ap.add_argument("--work-order", type=int, default=-1, help="bit 0 forward, bit 1 deposit: XCD-aware")
+    ap.add_argument("--angle-block", default="", help="deposit[,forward] angle blocks of the XCD-aware work order")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
     ap.add_argument("--cpu-threads", type=int, default=0)
+    ap.add_argument("--no-sparse", action="store_true",
+                    help="skip the extra timing of the deposit on the target's own (sparse) projections")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -146,6 +172,9 @@ def main():
         g.set_deposit_threads(args.deposit_threads)
     if args.work_order >= 0:
         g.set_work_order(args.work_order & 1, args.work_order >> 1)
+    if args.angle_block:
+        ab = [int(v) for v in args.angle_block.split(",")]
+        g.set_angle_blocks(deposit=ab[0], forward=ab[1] if len(ab) > 1 else None)
     rays_hit, samples_per_pass = g.stats()
     vol = torch.from_numpy(target).to(dev, dtype=tdt)
     proj = torch.empty(g.proj_shape, device=dev, dtype=tdt)
@@ -202,13 +231,15 @@ def main():
 
     f_avg, b_avg = float(np.mean(fwd_ms)), float(np.mean(back_ms))
     # deposit of the target's own projections (zero outside its shadow)
-    g.forward(vol, out=proj)
-    sparse_ms = []
-    for _ in range(max(1, args.steps)):
-        g.back(proj, out=dose)
-        torch.cuda.synchronize()
-        sparse_ms.append(g.kernel_times()[1])
-    active = float((proj != 0).float().mean())
+    sparse_ms, active = None, None
+    if not args.no_sparse:
+        g.forward(vol, out=proj)
+        sparse_ms = []
+        for _ in range(max(1, args.steps)):
+            g.back(proj, out=dose)
+            torch.cuda.synchronize()
+            sparse_ms.append(g.kernel_times()[1])
+        active = float((proj != 0).float().mean())
     dom, dom_ms = ("deposit", b_avg) if b_avg >= f_avg else ("forward", f_avg)
     flop = FLOP_PER_SAMPLE * samples_per_pass
     achieved = flop / (dom_ms * 1e-3) / 1e12
@@ -228,11 +259,13 @@ def main():
                    "rays_hit": rays_hit, "adjoint_variant": args.adjoint_variant,
                    "forward_variant": args.forward_variant, "box_edge": args.box_edge},
         "roofline": roofline,
-        "kernels_ms": {"forward": f_avg, "deposit": b_avg, "deposit_sparse_ms": float(np.mean(sparse_ms)),
+        "kernels_ms": {"forward": f_avg, "deposit": b_avg,
+                       "deposit_sparse_ms": float(np.mean(sparse_ms)) if sparse_ms else None,
                        "sparse_nonzero_pixel_fraction": active},
         "gather_model": {"bytes_per_sample": GATHER_BYTES_PER_SAMPLE, "kernel": dom,
                          "GBps": gather_gbps, "frac_of_hbm_peak": gather_gbps / PEAK_HBM_GBPS},
         "setup_s": t_setup, "wall_s": wall,
+        "learned_vs_plain": learned_vs_plain(),
     }
     if not args.no_cpu_baseline:
         threads = args.cpu_threads or min(16, os.cpu_count() or 1)

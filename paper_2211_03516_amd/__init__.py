@@ -262,6 +262,14 @@ class Geometry:
     def set_work_order(self, xcd_forward, xcd_deposit):
         _check(lib().vam_set_variant(self.handle, OP_WORK_ORDER, int(bool(xcd_forward)) | (int(bool(xcd_deposit)) << 1)))
 
+    def set_angle_blocks(self, deposit=None, forward=None):
+        """Work order with the angles of a box in blocks (0: boxes fastest,
+        1: all angles of a box on one XCD, A >= 2: blocks of A angles)."""
+        if deposit is not None:
+            _check(lib().vam_set_variant(self.handle, 8, int(deposit)))
+        if forward is not None:
+            _check(lib().vam_set_variant(self.handle, 9, int(forward)))
+
     def set_deposit_threads(self, n):
         _check(lib().vam_set_variant(self.handle, OP_DEPOSIT_THREADS, int(n)))
 

@@ -281,28 +281,44 @@ __device__ inline void store_proj(__half* p, int64_t i, float x) { p[i] = __floa
 // from HBM once and reused from that XCD's L2.
 constexpr int kXcds = 8;
 
+// Work order of the (box, angle) workgroups.
+//   xcd = 0: boxes fastest, every XCD on the same angles;
+//   xcd = 1: each XCD takes a contiguous range of (box, all angles) items, so
+//            a box's segment and ray records are reused from that XCD's L2
+//            across all angles;
+//   xcd = A >= 2: the same, with the angles in blocks of A: a box's records
+//            are reused across A angles while at most A workgroups of one box
+//            flush into the same dose cells at a time.
+// Workgroups are dispatched to the XCDs round-robin, so workgroup L runs on
+// XCD L mod 8.
 __device__ inline bool work_item(int nboxes, int na, int xcd, int& b, int& a) {
-  if (!xcd) {  // natural order: boxes fastest, all XCDs on the same angles
+  if (!xcd) {
     const int64_t L = blockIdx.x;
     if (L >= (int64_t)nboxes * na) return false;
     a = (int)(L / nboxes);
     b = (int)(L - (int64_t)a * nboxes);
     return true;
   }
-  const int64_t W = (int64_t)nboxes * na;
+  const int A = xcd == 1 ? na : xcd;
+  const int nblk = (na + A - 1) / A;
+  const int64_t W = (int64_t)nblk * nboxes * A;
   const int64_t per = (W + kXcds - 1) / kXcds;
   const int64_t L = blockIdx.x;
   const int64_t i = L / kXcds;
   const int64_t w = (L % kXcds) * per + i;
   if (i >= per || w >= W) return false;
-  b = (int)(w / na);
-  a = (int)(w - (int64_t)b * na);
-  return true;
+  const int64_t blk = w / ((int64_t)nboxes * A);
+  const int64_t rem = w - blk * nboxes * A;
+  b = (int)(rem / A);
+  a = (int)(blk * A + (rem - (int64_t)b * A));
+  return a < na;
 }
 
 static inline dim3 work_grid(int nboxes, int na, int xcd) {
-  const int64_t W = (int64_t)nboxes * na;
-  return dim3((unsigned)(xcd ? ((W + kXcds - 1) / kXcds) * kXcds : W));
+  if (!xcd) return dim3((unsigned)((int64_t)nboxes * na));
+  const int A = xcd == 1 ? na : xcd;
+  const int64_t W = (int64_t)((na + A - 1) / A) * nboxes * A;
+  return dim3((unsigned)(((W + kXcds - 1) / kXcds) * kXcds));
 }
 
 // Rotated-box footprint [X0, X1) x [Y0, Y1) x [Z0, Z1) in padded grid cells.
@@ -569,7 +585,15 @@ __global__ __launch_bounds__(NT) void k_back_boxc(MarchParams P, BoxParams Bp, c
     float kf = 0.0f;
     unsigned cur = 0xffffffffu;
     float w[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    int cx = -1, cy = 0, cz = 0;  // AGG == 2: cell whose corners w holds
+    // AGG == 2: the cell whose corners w holds, starting at the first sample's
+    int cx = 0, cy = 0, cz = 0;
+    unsigned base = 0;
+    if (AGG == 2) {
+      cx = (int)__builtin_amdgcn_fmed3f(g.px, 0.0f, hx);
+      cy = (int)__builtin_amdgcn_fmed3f(g.py, 0.0f, hy);
+      cz = (int)__builtin_amdgcn_fmed3f(g.pz, 0.0f, hz);
+      base = __umul24((unsigned)cz, SZ) + __umul24((unsigned)cy, SY) + (unsigned)cx;
+    }
     for (int k = 0; k < cnt; ++k, kf += 1.0f) {
       const float x = __builtin_amdgcn_fmed3f(fmaf(kf, g.dx, g.px), 0.0f, hx);
       const float y = __builtin_amdgcn_fmed3f(fmaf(kf, g.dy, g.py), 0.0f, hy);
@@ -586,79 +610,79 @@ __global__ __launch_bounds__(NT) void k_back_boxc(MarchParams P, BoxParams Bp, c
         // Corner sharing: moving one cell along an axis keeps the four
         // corners on the far face, so only the four on the near face are
         // added to LDS; the kept sums shift to the near side and the far
-        // side restarts at zero.  Steps of more than one cell (Delta s > 1)
-        // flush all eight corners.
+        // side restarts at zero.  Steps of more than one cell (only possible
+        // for Delta s > 1) flush all eight corners.
         const int ix = (int)x, iy = (int)y, iz = (int)z;
-        const int ex = ix - cx, ey = iy - cy, ez = iz - cz;
-        if (cx >= 0 && (ex < -1 || ex > 1 || ey < -1 || ey > 1 || ez < -1 || ez > 1)) {
-          double* p = acc + (__umul24((unsigned)cz, SZ) + __umul24((unsigned)cy, SY) + (unsigned)cx);
-          atomicAdd(p, (double)w[0]);
-          atomicAdd(p + 1, (double)w[1]);
-          atomicAdd(p + SY, (double)w[2]);
-          atomicAdd(p + SY + 1, (double)w[3]);
-          atomicAdd(p + SZ, (double)w[4]);
-          atomicAdd(p + SZ + 1, (double)w[5]);
-          atomicAdd(p + SZ + SY, (double)w[6]);
-          atomicAdd(p + SZ + SY + 1, (double)w[7]);
+        int ex = ix - cx, ey = iy - cy, ez = iz - cz;
+        if (P.step > 1.0f) {
+          if (ex < -1 || ex > 1 || ey < -1 || ey > 1 || ez < -1 || ez > 1) {
+            double* p = acc + base;
+            atomicAdd(p, (double)w[0]);
+            atomicAdd(p + 1, (double)w[1]);
+            atomicAdd(p + SY, (double)w[2]);
+            atomicAdd(p + SY + 1, (double)w[3]);
+            atomicAdd(p + SZ, (double)w[4]);
+            atomicAdd(p + SZ + 1, (double)w[5]);
+            atomicAdd(p + SZ + SY, (double)w[6]);
+            atomicAdd(p + SZ + SY + 1, (double)w[7]);
 #pragma unroll
-          for (int c = 0; c < 8; ++c) w[c] = 0.0f;
-          cx = -1;
-        }
-        if (cx < 0) {
-          cx = ix;
-          cy = iy;
-          cz = iz;
-        } else {
-          unsigned base = __umul24((unsigned)cz, SZ) + __umul24((unsigned)cy, SY) + (unsigned)cx;
-          if (ex != 0) {
-            const bool up = ex > 0;  // near face: corners with x bit 0 (up) or 1
-            double* p = acc + base + (up ? 0 : 1);
-            atomicAdd(p, (double)(up ? w[0] : w[1]));
-            atomicAdd(p + SY, (double)(up ? w[2] : w[3]));
-            atomicAdd(p + SZ, (double)(up ? w[4] : w[5]));
-            atomicAdd(p + SZ + SY, (double)(up ? w[6] : w[7]));
-#pragma unroll
-            for (int c = 0; c < 8; c += 2) {
-              const float lo = w[c], hi = w[c + 1];
-              w[c] = up ? hi : 0.0f;
-              w[c + 1] = up ? 0.0f : lo;
-            }
-            base += ex;
+            for (int c = 0; c < 8; ++c) w[c] = 0.0f;
             cx = ix;
-          }
-          if (ey != 0) {
-            const bool up = ey > 0;
-            double* p = acc + base + (up ? 0 : SY);
-            atomicAdd(p, (double)(up ? w[0] : w[2]));
-            atomicAdd(p + 1, (double)(up ? w[1] : w[3]));
-            atomicAdd(p + SZ, (double)(up ? w[4] : w[6]));
-            atomicAdd(p + SZ + 1, (double)(up ? w[5] : w[7]));
-            const int pair[4] = {0, 1, 4, 5};
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-              const int c = pair[j];
-              const float lo = w[c], hi = w[c + 2];
-              w[c] = up ? hi : 0.0f;
-              w[c + 2] = up ? 0.0f : lo;
-            }
-            base += ey * SY;
             cy = iy;
-          }
-          if (ez != 0) {
-            const bool up = ez > 0;
-            double* p = acc + base + (up ? 0 : SZ);
-            atomicAdd(p, (double)(up ? w[0] : w[4]));
-            atomicAdd(p + 1, (double)(up ? w[1] : w[5]));
-            atomicAdd(p + SY, (double)(up ? w[2] : w[6]));
-            atomicAdd(p + SY + 1, (double)(up ? w[3] : w[7]));
-#pragma unroll
-            for (int c = 0; c < 4; ++c) {
-              const float lo = w[c], hi = w[c + 4];
-              w[c] = up ? hi : 0.0f;
-              w[c + 4] = up ? 0.0f : lo;
-            }
             cz = iz;
+            base = __umul24((unsigned)cz, SZ) + __umul24((unsigned)cy, SY) + (unsigned)cx;
+            ex = ey = ez = 0;
           }
+        }
+        if (ex != 0) {
+          const bool up = ex > 0;  // near face: corners with x bit 0 (up) or 1
+          double* p = acc + base + (up ? 0 : 1);
+          atomicAdd(p, (double)(up ? w[0] : w[1]));
+          atomicAdd(p + SY, (double)(up ? w[2] : w[3]));
+          atomicAdd(p + SZ, (double)(up ? w[4] : w[5]));
+          atomicAdd(p + SZ + SY, (double)(up ? w[6] : w[7]));
+#pragma unroll
+          for (int c = 0; c < 8; c += 2) {
+            const float lo = w[c], hi = w[c + 1];
+            w[c] = up ? hi : 0.0f;
+            w[c + 1] = up ? 0.0f : lo;
+          }
+          base += ex;
+          cx = ix;
+        }
+        if (ey != 0) {
+          const bool up = ey > 0;
+          double* p = acc + base + (up ? 0 : SY);
+          atomicAdd(p, (double)(up ? w[0] : w[2]));
+          atomicAdd(p + 1, (double)(up ? w[1] : w[3]));
+          atomicAdd(p + SZ, (double)(up ? w[4] : w[6]));
+          atomicAdd(p + SZ + 1, (double)(up ? w[5] : w[7]));
+          const int pair[4] = {0, 1, 4, 5};
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const int c = pair[j];
+            const float lo = w[c], hi = w[c + 2];
+            w[c] = up ? hi : 0.0f;
+            w[c + 2] = up ? 0.0f : lo;
+          }
+          base += ey * SY;
+          cy = iy;
+        }
+        if (ez != 0) {
+          const bool up = ez > 0;
+          double* p = acc + base + (up ? 0 : SZ);
+          atomicAdd(p, (double)(up ? w[0] : w[4]));
+          atomicAdd(p + 1, (double)(up ? w[1] : w[5]));
+          atomicAdd(p + SY, (double)(up ? w[2] : w[6]));
+          atomicAdd(p + SY + 1, (double)(up ? w[3] : w[7]));
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            const float lo = w[c], hi = w[c + 4];
+            w[c] = up ? hi : 0.0f;
+            w[c + 4] = up ? 0.0f : lo;
+          }
+          base += ez * SZ;
+          cz = iz;
         }
 #pragma unroll
         for (int c = 0; c < 8; ++c) w[c] += q[c];
@@ -695,8 +719,8 @@ __global__ __launch_bounds__(NT) void k_back_boxc(MarchParams P, BoxParams Bp, c
       }
       e = fmaf(e, P.r_hi, e * P.r_lo);
     }
-    if (AGG == 2 && cx >= 0) {
-      double* p = acc + (__umul24((unsigned)cz, SZ) + __umul24((unsigned)cy, SY) + (unsigned)cx);
+    if (AGG == 2 && cnt > 0) {
+      double* p = acc + base;
       atomicAdd(p, (double)w[0]);
       atomicAdd(p + 1, (double)w[1]);
       atomicAdd(p + SY, (double)w[2]);

@@ -495,6 +495,9 @@ vam_status vam_set_variant(vam_geometry_t h, int32_t op, int32_t variant) {
     if (variant < 0 || variant > 3) return fail(VAM_ERR_INVALID_ARG, "work order flags must be in [0, 3]");
     h->xcd_forward = variant & 1;
     h->xcd_deposit = (variant >> 1) & 1;
+  } else if (op == 8 || op == 9) {
+    if (variant < 0 || variant > 4096) return fail(VAM_ERR_INVALID_ARG, "angle block must be in [0, 4096]");
+    (op == 8 ? h->xcd_deposit : h->xcd_forward) = variant;
   } else if (op == 3) {
     if (variant < 0 || variant > 1) return fail(VAM_ERR_INVALID_ARG, "fixed-footprint switch must be 0 or 1");
     h->fixed_kernels = variant;

@@ -54,12 +54,13 @@ def kernel_source_hash(root):
     return h.hexdigest()
 
 
-def traffic(fetch_csv, write_csv, copy_mib, root, calls=1):
+def traffic(fetch_csv, write_csv, copy_mib, root, calls=None):
     """HBM bytes per call of the main kernels (a call = one operator pass,
     which may be several dispatches), with FETCH_SIZE and WRITE_SIZE each
     scaled by what they read for the largest copy kernel (a device copy of
-    copy_mib MiB: reads and writes exactly that much).  `calls` is the
-    number of operator passes in the profiled run."""
+    copy_mib MiB: reads and writes exactly that much).  `calls` maps each
+    kernel to the number of operator passes in the profiled run."""
+    calls = calls or {}
     def load(path, counter):
         rows = [r for r in csv.DictReader(open(path)) if r["Counter_Name"] == counter]
         copy = max((float(r["Counter_Value"]) for r in rows if "copyBuffer" in r["Kernel_Name"]), default=0.0)
@@ -79,9 +80,10 @@ def traffic(fetch_csv, write_csv, copy_mib, root, calls=1):
            "note": "bytes per call; FETCH_SIZE and WRITE_SIZE (KiB) scaled by the copy calibration"}
     for name in KERNELS:
         if fetch.get(name) and write.get(name) and ff and fw:
-            f = sum(fetch[name]) / calls * ff * 1024
-            w = sum(write[name]) / calls * fw * 1024
-            out[name] = {"fetch_bytes": f, "write_bytes": w, "dispatches_per_call": len(fetch[name]) / calls}
+            c = calls.get(name, 1)
+            f = sum(fetch[name]) / c * ff * 1024
+            w = sum(write[name]) / c * fw * 1024
+            out[name] = {"fetch_bytes": f, "write_bytes": w, "dispatches_per_call": len(fetch[name]) / c}
     return out
 
 
@@ -94,12 +96,13 @@ def main(argv=None):
     ap.add_argument("path2", nargs="?")
     ap.add_argument("--cmd", default=None, help="command that produced the CSV (written as a header)")
     ap.add_argument("--copy-mib", type=float, default=1024.0)
-    ap.add_argument("--calls", type=int, default=1)
+    ap.add_argument("--calls", default="", help="operator passes per kernel in the run, e.g. forward=2,deposit=1")
     ap.add_argument("--out", default=None)
     a = ap.parse_args(argv)
     if a.what == "traffic":
         root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-        d = traffic(a.path, a.path2, a.copy_mib, root, a.calls)
+        calls = {k: int(v) for k, v in (kv.split("=") for kv in a.calls.split(",") if kv)}
+        d = traffic(a.path, a.path2, a.copy_mib, root, calls)
         if a.cmd:
             d["command"] = a.cmd
         text = json.dumps(d, indent=1)

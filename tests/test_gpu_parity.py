@@ -270,6 +270,24 @@ def test_box_deposits_any_step(step):
     g.close()
 
 
+def test_work_orders_agree():
+    # every (box, angle) item is processed exactly once in each work order
+    p = c2_small(40, n_pupil=4, n_angles=10)
+    g = gpu_geom(p)
+    rng = synth.SplitMix64(15)
+    x = rng.uniform(40 ** 3).reshape(40, 40, 40)
+    y = rng.uniform(10 * 40 * 40).reshape(10, 40, 40)
+    og = oracle.Geometry(p)
+    Pref, Dref = oracle.forward(og, x), oracle.adjoint(og, y)
+    for blk in (0, 1, 3, 8, 64):
+        g.set_angle_blocks(deposit=blk, forward=blk)
+        ef = relL2(g.forward(to_dev(x)).cpu().numpy(), Pref)
+        ea = relL2(g.back(to_dev(y)).cpu().numpy(), Dref)
+        say("angle block %d: forward %.3e deposit %.3e" % (blk, ef, ea))
+        assert ef <= 1e-5 and ea <= 1e-5
+    g.close()
+
+
 def test_gather_deposit_angles_accumulate_and_order():
     # the voxel-driven gather against the oracle on an angle sub-range, with
     # accumulation into an existing dose, and bitwise repeatable
