@@ -214,7 +214,11 @@ vam_status vam_export_rays(vam_geometry_t h, double* out);
  *                   use, ~32 bytes per run; no atomics, fixed order),
  *                   10 = as 8, but consecutive cells share the corners of
  *                   their common face in registers (four LDS adds per cell
- *                   crossed instead of eight).
+ *                   crossed instead of eight), 11, 12, 13 = as 8, 10, 6
+ *                   with the footprint summed in 32-bit fixed point (the
+ *                   scale of each box and angle bounds every partial sum
+ *                   below 2^31; rounding <= 2^-31 of that bound per add; a
+ *                   non-finite projection value makes its footprint NaN).
  *   op 2, tiling:   variant = lab-box edge in voxels, from 4 up to the
  *                   largest edge whose FP64 footprint fits in the 160 KiB
  *                   of LDS (19 for grids of 24^3 voxels and more); rebuilds
@@ -225,8 +229,8 @@ vam_status vam_export_rays(vam_geometry_t h, double* out);
  *   op 4, order:    order of the segments inside a box for the deposit:
  *                   0 = by ray, 1 = by decreasing length, 2 = by pixel
  *                   parity class then ray (default); rebuilds the boxes.
- *   op 5, threads:  workgroup size of the fixed-footprint deposit, 256 or
- *                   512 (default).
+ *   op 5, threads:  workgroup size of the fixed-footprint deposit, 256
+ *                   (default) or 512.
  *   op 6, order:    work order of the box kernels, bit 0 forward, bit 1
  *                   deposit: 0 = boxes fastest (all XCDs work on the same
  *                   angles), 1 = XCD-aware (each XCD walks a contiguous

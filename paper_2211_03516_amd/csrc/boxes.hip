@@ -119,11 +119,68 @@ struct BoxParams {
   int wxy_max, wz_max;
   int npix;            // n_u * n_v
   int px, py, pz;
+  double supp_coef;    // integer LDS accumulation: n_supp * step / n_pupil
 };
 
 BoxParams box_params(const vam_geometry* h);
 
+// Samples per lab-frame unit cell (x, y from -R, padded z), from the same
+// positions the marching kernels use (midpoint + t direction, FP64).
+__global__ void k_lab_count(const RayRec* rays, int64_t n_rays, double step, double x0, int ncx, int ncz,
+                            unsigned* count) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n_rays) return;
+  const RayRec R = rays[r];
+  for (int k = R.k0; k < R.k0 + R.n; ++k) {
+    const double t = ((double)k + 0.5 - 0.5 * (double)R.K) * step;
+    const int ix = min(max((int)floor(R.mx + t * R.dx - x0), 0), ncx - 1);
+    const int iy = min(max((int)floor(R.my + t * R.dy - x0), 0), ncx - 1);
+    const int iz = min(max((int)floor((double)R.gz + t * (double)R.dz), 0), ncz - 1);
+    atomicAdd(count + ((int64_t)iz * ncx + iy) * ncx + ix, 1u);
+  }
+}
+
+// Largest sample count of any 4 x 4 x 3 block of cells.
+__global__ void k_window_max(const unsigned* count, int ncx, int ncz, unsigned* out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)ncx * ncx * ncz) return;
+  const int ix = (int)(i % ncx), iy = (int)((i / ncx) % ncx), iz = (int)(i / ((int64_t)ncx * ncx));
+  unsigned sum = 0;
+  for (int dz = 0; dz < 3 && iz + dz < ncz; ++dz)
+    for (int dy = 0; dy < 4 && iy + dy < ncx; ++dy)
+      for (int dx = 0; dx < 4 && ix + dx < ncx; ++dx) sum += count[((int64_t)(iz + dz) * ncx + iy + dy) * ncx + ix + dx];
+  atomicMax(out, sum);
+}
+
+// n_supp of the integer LDS deposit (synchronises the stream).
+static vam_status support_bound(vam_geometry* h, hipStream_t s) {
+  const double R = h->desc.r_inner + 1.0;
+  const int ncx = (int)std::ceil(2.0 * R), ncz = h->pz;
+  const int64_t ncell = (int64_t)ncx * ncx * ncz;
+  unsigned* count = nullptr;
+  VAM_HIP_TRY(hipMalloc(&count, (ncell + 1) * sizeof(unsigned)), "allocating lab cell counts");
+  unsigned* out = count + ncell;
+  hipError_t e = hipMemsetAsync(count, 0, (ncell + 1) * sizeof(unsigned), s);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_lab_count, dim3((unsigned)((h->n_rays + 255) / 256)), dim3(256), 0, s, h->rays, h->n_rays,
+                       h->desc.step, -R, ncx, ncz, count);
+    hipLaunchKernelGGL(k_window_max, dim3((unsigned)((ncell + 255) / 256)), dim3(256), 0, s, count, ncx, ncz, out);
+    e = hipGetLastError();
+  }
+  unsigned hmax = 0;
+  if (e == hipSuccess) e = hipMemcpyAsync(&hmax, out, sizeof(unsigned), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(count);
+  if (e != hipSuccess) return hip_check(e, "bounding samples per voxel support");
+  h->n_supp = std::max<int64_t>(hmax, 1);
+  return VAM_OK;
+}
+
 vam_status build_boxes(vam_geometry* h, hipStream_t s) {
+  if (h->n_supp == 0) {
+    vam_status st = support_bound(h, s);
+    if (st != VAM_OK) return st;
+  }
   const vam_geometry_desc& D = h->desc;
   BoxGrid G;
   G.B = h->box_edge > 0 ? h->box_edge : kBox;
@@ -560,20 +617,74 @@ __global__ __launch_bounds__(256) void k_forward_boxc(MarchParams P, BoxParams B
   }
 }
 
-template <int B, typename PT, int AGG, int NT>
+// LDS adds of the deposit: FP64, or 32-bit integers in fixed point with the
+// workgroup's scale S (rounded to nearest).
+template <typename LT>
+__device__ inline void lds_add(LT* p, float v, float S);
+template <>
+__device__ inline void lds_add<double>(double* p, float v, float) {
+  atomicAdd(p, (double)v);
+}
+template <>
+__device__ inline void lds_add<int>(int* p, float v, float S) {
+  atomicAdd(p, (int)__builtin_rintf(v * S));
+}
+
+// LT = int: the footprint is accumulated in 32-bit fixed point (gfx950 adds
+// 32-bit integers in LDS about twice as fast as FP64).  Overflow is ruled
+// out per workgroup: a cell's sum is bounded by (samples inside one voxel's
+// support) x (largest sample weight), where the first factor is n_supp, the
+// most samples of all rays in any 4 x 4 x 3 block of lab-frame unit cells
+// (the turned support of a voxel fits in such a block), and the second is
+// step / n_pupil times the largest |projection value| among the box's
+// segments at this angle.  S is the power of two that maps that bound to at
+// most 2^30, so every partial sum stays below 2^31 and S is exact; the
+// rounding error of an add is at most 1/(2S).  A non-finite projection value
+// makes the whole footprint NaN.
+template <int B, typename PT, int AGG, int NT, typename LT>
 __global__ __launch_bounds__(NT) void k_back_boxc(MarchParams P, BoxParams Bp, const PT* __restrict__ proj,
                                                   double* __restrict__ dose) {
   constexpr int SY = Fixed<B>::WXY, SZ = SY * SY, NC = SZ * Fixed<B>::WZ;
-  __shared__ double acc[NC];
+  constexpr bool kInt = sizeof(LT) == 4;
+  __shared__ LT acc[NC];
+  __shared__ unsigned s_pvmax;
+  __shared__ int s_bad;
   int b, a;
   if (!work_item(Bp.nboxes, Bp.na, Bp.xcd, b, a)) return;
   const double2 cs = P.cs[P.a0 + a];
   const Foot f = footprint(Bp, Bp.box_id[b], cs.x, cs.y, P.cx, P.cy);
-  for (int i = threadIdx.x; i < NC; i += blockDim.x) acc[i] = 0.0;
+  for (int i = threadIdx.x; i < NC; i += blockDim.x) acc[i] = (LT)0;
+  if (kInt && threadIdx.x == 0) {
+    s_pvmax = 0u;
+    s_bad = 0;
+  }
   __syncthreads();
   const float hx = (float)f.WX - 1.001f, hy = (float)f.WY - 1.001f, hz = (float)f.WZ - 1.001f;
   const int64_t pbase = (int64_t)a * Bp.npix;
   const int s_end = Bp.box_begin[b + 1];
+  float S = 1.0f;
+  double invS = 1.0;
+  bool bad = false;
+  if (kInt) {
+    float m = 0.0f;
+    bool nonfinite = false;
+    for (int si = Bp.box_begin[b] + threadIdx.x; si < s_end; si += blockDim.x) {
+      const float apv = fabsf(load_p(proj, pbase + Bp.segs[si].x % Bp.npix));
+      if (apv <= 3.4028234e38f)
+        m = fmaxf(m, apv);
+      else
+        nonfinite = true;
+    }
+    atomicMax(&s_pvmax, __float_as_uint(m));  // non-negative floats order as their bits
+    if (nonfinite) atomicOr(&s_bad, 1);
+    __syncthreads();
+    bad = s_bad != 0;
+    const double bound = Bp.supp_coef * (double)__uint_as_float(s_pvmax);
+    int e2 = 0;
+    if (bound > 0.0) e2 = min(max((int)floor(log2(1073741824.0 / bound)), -120), 120);
+    S = ldexpf(1.0f, e2);
+    invS = ldexp(1.0, -e2);
+  }
   for (int si = Bp.box_begin[b] + threadIdx.x; si < s_end; si += blockDim.x) {
     const int4 sg = Bp.segs[si];
     const int r = sg.x, cnt = sg.z;
@@ -616,15 +727,15 @@ __global__ __launch_bounds__(NT) void k_back_boxc(MarchParams P, BoxParams Bp, c
         int ex = ix - cx, ey = iy - cy, ez = iz - cz;
         if (P.step > 1.0f) {
           if (ex < -1 || ex > 1 || ey < -1 || ey > 1 || ez < -1 || ez > 1) {
-            double* p = acc + base;
-            atomicAdd(p, (double)w[0]);
-            atomicAdd(p + 1, (double)w[1]);
-            atomicAdd(p + SY, (double)w[2]);
-            atomicAdd(p + SY + 1, (double)w[3]);
-            atomicAdd(p + SZ, (double)w[4]);
-            atomicAdd(p + SZ + 1, (double)w[5]);
-            atomicAdd(p + SZ + SY, (double)w[6]);
-            atomicAdd(p + SZ + SY + 1, (double)w[7]);
+            LT* p = acc + base;
+            lds_add(p, w[0], S);
+            lds_add(p + 1, w[1], S);
+            lds_add(p + SY, w[2], S);
+            lds_add(p + SY + 1, w[3], S);
+            lds_add(p + SZ, w[4], S);
+            lds_add(p + SZ + 1, w[5], S);
+            lds_add(p + SZ + SY, w[6], S);
+            lds_add(p + SZ + SY + 1, w[7], S);
 #pragma unroll
             for (int c = 0; c < 8; ++c) w[c] = 0.0f;
             cx = ix;
@@ -636,11 +747,11 @@ __global__ __launch_bounds__(NT) void k_back_boxc(MarchParams P, BoxParams Bp, c
         }
         if (ex != 0) {
           const bool up = ex > 0;  // near face: corners with x bit 0 (up) or 1
-          double* p = acc + base + (up ? 0 : 1);
-          atomicAdd(p, (double)(up ? w[0] : w[1]));
-          atomicAdd(p + SY, (double)(up ? w[2] : w[3]));
-          atomicAdd(p + SZ, (double)(up ? w[4] : w[5]));
-          atomicAdd(p + SZ + SY, (double)(up ? w[6] : w[7]));
+          LT* p = acc + base + (up ? 0 : 1);
+          lds_add(p, (up ? w[0] : w[1]), S);
+          lds_add(p + SY, (up ? w[2] : w[3]), S);
+          lds_add(p + SZ, (up ? w[4] : w[5]), S);
+          lds_add(p + SZ + SY, (up ? w[6] : w[7]), S);
 #pragma unroll
           for (int c = 0; c < 8; c += 2) {
             const float lo = w[c], hi = w[c + 1];
@@ -652,11 +763,11 @@ __global__ __launch_bounds__(NT) void k_back_boxc(MarchParams P, BoxParams Bp, c
         }
         if (ey != 0) {
           const bool up = ey > 0;
-          double* p = acc + base + (up ? 0 : SY);
-          atomicAdd(p, (double)(up ? w[0] : w[2]));
-          atomicAdd(p + 1, (double)(up ? w[1] : w[3]));
-          atomicAdd(p + SZ, (double)(up ? w[4] : w[6]));
-          atomicAdd(p + SZ + 1, (double)(up ? w[5] : w[7]));
+          LT* p = acc + base + (up ? 0 : SY);
+          lds_add(p, (up ? w[0] : w[2]), S);
+          lds_add(p + 1, (up ? w[1] : w[3]), S);
+          lds_add(p + SZ, (up ? w[4] : w[6]), S);
+          lds_add(p + SZ + 1, (up ? w[5] : w[7]), S);
           const int pair[4] = {0, 1, 4, 5};
 #pragma unroll
           for (int j = 0; j < 4; ++j) {
@@ -670,11 +781,11 @@ __global__ __launch_bounds__(NT) void k_back_boxc(MarchParams P, BoxParams Bp, c
         }
         if (ez != 0) {
           const bool up = ez > 0;
-          double* p = acc + base + (up ? 0 : SZ);
-          atomicAdd(p, (double)(up ? w[0] : w[4]));
-          atomicAdd(p + 1, (double)(up ? w[1] : w[5]));
-          atomicAdd(p + SY, (double)(up ? w[2] : w[6]));
-          atomicAdd(p + SY + 1, (double)(up ? w[3] : w[7]));
+          LT* p = acc + base + (up ? 0 : SZ);
+          lds_add(p, (up ? w[0] : w[4]), S);
+          lds_add(p + 1, (up ? w[1] : w[5]), S);
+          lds_add(p + SY, (up ? w[2] : w[6]), S);
+          lds_add(p + SY + 1, (up ? w[3] : w[7]), S);
 #pragma unroll
           for (int c = 0; c < 4; ++c) {
             const float lo = w[c], hi = w[c + 4];
@@ -689,15 +800,15 @@ __global__ __launch_bounds__(NT) void k_back_boxc(MarchParams P, BoxParams Bp, c
       } else if (AGG) {
         if (o != cur) {
           if (cur != 0xffffffffu) {
-            double* p = acc + cur;
-            atomicAdd(p, (double)w[0]);
-            atomicAdd(p + 1, (double)w[1]);
-            atomicAdd(p + SY, (double)w[2]);
-            atomicAdd(p + SY + 1, (double)w[3]);
-            atomicAdd(p + SZ, (double)w[4]);
-            atomicAdd(p + SZ + 1, (double)w[5]);
-            atomicAdd(p + SZ + SY, (double)w[6]);
-            atomicAdd(p + SZ + SY + 1, (double)w[7]);
+            LT* p = acc + cur;
+            lds_add(p, w[0], S);
+            lds_add(p + 1, w[1], S);
+            lds_add(p + SY, w[2], S);
+            lds_add(p + SY + 1, w[3], S);
+            lds_add(p + SZ, w[4], S);
+            lds_add(p + SZ + 1, w[5], S);
+            lds_add(p + SZ + SY, w[6], S);
+            lds_add(p + SZ + SY + 1, w[7], S);
           }
           cur = o;
 #pragma unroll
@@ -707,48 +818,49 @@ __global__ __launch_bounds__(NT) void k_back_boxc(MarchParams P, BoxParams Bp, c
           for (int c = 0; c < 8; ++c) w[c] += q[c];
         }
       } else {
-        double* p = acc + o;
-        atomicAdd(p, (double)q[0]);
-        atomicAdd(p + 1, (double)q[1]);
-        atomicAdd(p + SY, (double)q[2]);
-        atomicAdd(p + SY + 1, (double)q[3]);
-        atomicAdd(p + SZ, (double)q[4]);
-        atomicAdd(p + SZ + 1, (double)q[5]);
-        atomicAdd(p + SZ + SY, (double)q[6]);
-        atomicAdd(p + SZ + SY + 1, (double)q[7]);
+        LT* p = acc + o;
+        lds_add(p, q[0], S);
+        lds_add(p + 1, q[1], S);
+        lds_add(p + SY, q[2], S);
+        lds_add(p + SY + 1, q[3], S);
+        lds_add(p + SZ, q[4], S);
+        lds_add(p + SZ + 1, q[5], S);
+        lds_add(p + SZ + SY, q[6], S);
+        lds_add(p + SZ + SY + 1, q[7], S);
       }
       e = fmaf(e, P.r_hi, e * P.r_lo);
     }
     if (AGG == 2 && cnt > 0) {
-      double* p = acc + base;
-      atomicAdd(p, (double)w[0]);
-      atomicAdd(p + 1, (double)w[1]);
-      atomicAdd(p + SY, (double)w[2]);
-      atomicAdd(p + SY + 1, (double)w[3]);
-      atomicAdd(p + SZ, (double)w[4]);
-      atomicAdd(p + SZ + 1, (double)w[5]);
-      atomicAdd(p + SZ + SY, (double)w[6]);
-      atomicAdd(p + SZ + SY + 1, (double)w[7]);
+      LT* p = acc + base;
+      lds_add(p, w[0], S);
+      lds_add(p + 1, w[1], S);
+      lds_add(p + SY, w[2], S);
+      lds_add(p + SY + 1, w[3], S);
+      lds_add(p + SZ, w[4], S);
+      lds_add(p + SZ + 1, w[5], S);
+      lds_add(p + SZ + SY, w[6], S);
+      lds_add(p + SZ + SY + 1, w[7], S);
     }
     if (AGG == 1 && cur != 0xffffffffu) {
-      double* p = acc + cur;
-      atomicAdd(p, (double)w[0]);
-      atomicAdd(p + 1, (double)w[1]);
-      atomicAdd(p + SY, (double)w[2]);
-      atomicAdd(p + SY + 1, (double)w[3]);
-      atomicAdd(p + SZ, (double)w[4]);
-      atomicAdd(p + SZ + 1, (double)w[5]);
-      atomicAdd(p + SZ + SY, (double)w[6]);
-      atomicAdd(p + SZ + SY + 1, (double)w[7]);
+      LT* p = acc + cur;
+      lds_add(p, w[0], S);
+      lds_add(p + 1, w[1], S);
+      lds_add(p + SY, w[2], S);
+      lds_add(p + SY + 1, w[3], S);
+      lds_add(p + SZ, w[4], S);
+      lds_add(p + SZ + 1, w[5], S);
+      lds_add(p + SZ + SY, w[6], S);
+      lds_add(p + SZ + SY + 1, w[7], S);
     }
   }
   __syncthreads();
   for (int i = threadIdx.x; i < NC; i += blockDim.x) {
-    const double v = acc[i];
-    if (v == 0.0) continue;
+    const LT raw = acc[i];
+    if (raw == (LT)0 && !bad) continue;
     const int z = i / SZ, rem = i - z * SZ, y = rem / SY, x = rem - y * SY;
+    if (x >= f.WX || y >= f.WY || z >= f.WZ) continue;
     const int64_t gi = ((int64_t)(f.Z0 + z) * Bp.py + (f.Y0 + y)) * Bp.px + (f.X0 + x);
-    unsafeAtomicAdd(dose + gi, v);
+    unsafeAtomicAdd(dose + gi, bad ? __builtin_nan("") : (double)raw * invS);
   }
 }
 
@@ -770,6 +882,7 @@ BoxParams box_params(const vam_geometry* h) {
   Bp.px = h->px;
   Bp.py = h->py;
   Bp.pz = h->pz;
+  Bp.supp_coef = (double)h->n_supp * h->desc.step / h->desc.n_pupil;
   return Bp;
 }
 
@@ -792,7 +905,7 @@ static void launch_box_k(vam_geometry* h, const MarchParams& P, const BoxParams&
                      h->dose_pad64);
 }
 
-template <int B, typename PT, int AGG>
+template <int B, typename PT, int AGG, typename LT>
 static void launch_boxc(vam_geometry* h, const MarchParams& P, const BoxParams& Bp, const PT* proj, int na,
                         hipStream_t s) {
   BoxParams Bw = Bp;
@@ -801,31 +914,50 @@ static void launch_boxc(vam_geometry* h, const MarchParams& P, const BoxParams& 
   Bw.xcd = h->xcd_deposit;
   const dim3 grid = work_grid(h->n_boxes, na, Bw.xcd);
   if (h->deposit_threads == 512)
-    hipLaunchKernelGGL((k_back_boxc<B, PT, AGG, 512>), grid, dim3(512), 0, s, P, Bw, proj, h->dose_pad64);
+    hipLaunchKernelGGL((k_back_boxc<B, PT, AGG, 512, LT>), grid, dim3(512), 0, s, P, Bw, proj, h->dose_pad64);
   else
-    hipLaunchKernelGGL((k_back_boxc<B, PT, AGG, 256>), grid, dim3(256), 0, s, P, Bw, proj, h->dose_pad64);
+    hipLaunchKernelGGL((k_back_boxc<B, PT, AGG, 256, LT>), grid, dim3(256), 0, s, P, Bw, proj, h->dose_pad64);
 }
 
+template <int B, typename PT, typename LT>
+static void launch_boxc_agg(vam_geometry* h, const MarchParams& P, const BoxParams& Bp, const PT* proj, int na,
+                            int agg, hipStream_t s) {
+  switch (agg) {
+    case 0: launch_boxc<B, PT, 0, LT>(h, P, Bp, proj, na, s); break;
+    case 1: launch_boxc<B, PT, 1, LT>(h, P, Bp, proj, na, s); break;
+    default: launch_boxc<B, PT, 2, LT>(h, P, Bp, proj, na, s); break;
+  }
+}
+
+template <typename PT, typename LT>
+static void launch_boxc_edge(vam_geometry* h, const MarchParams& P, const BoxParams& Bp, const PT* proj, int na,
+                             int agg, hipStream_t s) {
+  switch (h->boxes.B) {
+    case 8: launch_boxc_agg<8, PT, LT>(h, P, Bp, proj, na, agg, s); break;
+    case 12: launch_boxc_agg<12, PT, LT>(h, P, Bp, proj, na, agg, s); break;
+    default: launch_boxc_agg<16, PT, LT>(h, P, Bp, proj, na, agg, s); break;
+  }
+}
+
+// Deposit variants of the box kernels: 6, 8, 10 accumulate the footprint in
+// FP64, 13, 11, 12 in 32-bit fixed point, each without aggregation, with
+// cell-run aggregation and with corner sharing.  Edges without a
+// fixed-footprint kernel use the runtime-stride FP64 kernels.
 template <typename PT>
 static void launch_box_t(vam_geometry* h, const MarchParams& P, const PT* proj, int na, int variant,
                          hipStream_t s) {
   const BoxParams Bp = box_params(h);
-  if ((variant == 6 || variant == 8 || variant == 10) && fixed_edge(h->boxes.B) && h->fixed_kernels) {
-    const int agg = variant == 10 ? 2 : variant == 8 ? 1 : 0;
-    switch (h->boxes.B * 4 + agg) {
-      case 8 * 4 + 0: launch_boxc<8, PT, 0>(h, P, Bp, proj, na, s); break;
-      case 8 * 4 + 1: launch_boxc<8, PT, 1>(h, P, Bp, proj, na, s); break;
-      case 8 * 4 + 2: launch_boxc<8, PT, 2>(h, P, Bp, proj, na, s); break;
-      case 12 * 4 + 0: launch_boxc<12, PT, 0>(h, P, Bp, proj, na, s); break;
-      case 12 * 4 + 1: launch_boxc<12, PT, 1>(h, P, Bp, proj, na, s); break;
-      case 12 * 4 + 2: launch_boxc<12, PT, 2>(h, P, Bp, proj, na, s); break;
-      case 16 * 4 + 0: launch_boxc<16, PT, 0>(h, P, Bp, proj, na, s); break;
-      case 16 * 4 + 1: launch_boxc<16, PT, 1>(h, P, Bp, proj, na, s); break;
-      default: launch_boxc<16, PT, 2>(h, P, Bp, proj, na, s); break;
-    }
+  const bool fixed = fixed_edge(h->boxes.B) && h->fixed_kernels;
+  const int agg = (variant == 10 || variant == 12) ? 2 : (variant == 8 || variant == 11) ? 1 : 0;
+  if (fixed && (variant == 6 || variant == 8 || variant == 10)) {
+    launch_boxc_edge<PT, double>(h, P, Bp, proj, na, agg, s);
     return;
   }
-  if (variant == 10) variant = 8;  // runtime-stride kernels: cell-run aggregation
+  if (fixed && variant >= 11) {
+    launch_boxc_edge<PT, int>(h, P, Bp, proj, na, agg, s);
+    return;
+  }
+  if (variant >= 10) variant = agg ? 8 : 6;
   switch (variant) {
     case 7: launch_box_k<PT, float, false>(h, P, Bp, proj, na, s); break;
     case 8: launch_box_k<PT, double, true>(h, P, Bp, proj, na, s); break;

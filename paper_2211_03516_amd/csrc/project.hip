@@ -456,7 +456,7 @@ static bool v2_eligible(const vam_geometry* h) {
 
 // Kernels used when the caller asks for the default (fastest measured).
 constexpr int kDefaultForwardVariant = 2;
-constexpr int kDefaultBackVariant = 10;
+constexpr int kDefaultBackVariant = 11;
 
 static inline unsigned blocks_for(int64_t n, int threads) { return (unsigned)((n + threads - 1) / threads); }
 

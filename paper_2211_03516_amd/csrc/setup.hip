@@ -354,7 +354,7 @@ vam_status vam_setup_geometry(const vam_geometry_desc* desc, hipStream_t stream,
   h->adjoint_variant = 0;
   h->fixed_kernels = 1;
   h->seg_order = 2;
-  h->deposit_threads = 512;
+  h->deposit_threads = 256;
   h->angles.resize(desc->n_angles);
   for (int a = 0; a < desc->n_angles; ++a)
     h->angles[a] = desc->angles_rad ? desc->angles_rad[a] : 2.0 * M_PI * a / desc->n_angles;
@@ -479,7 +479,7 @@ vam_status vam_set_variant(vam_geometry_t h, int32_t op, int32_t variant) {
     if (variant < 0 || variant > 3) return fail(VAM_ERR_INVALID_ARG, "unknown forward variant %d", variant);
     h->forward_variant = variant;
   } else if (op == 1) {
-    if (variant < 0 || variant > 10) return fail(VAM_ERR_INVALID_ARG, "unknown deposit variant %d", variant);
+    if (variant < 0 || variant > 13) return fail(VAM_ERR_INVALID_ARG, "unknown deposit variant %d", variant);
     h->adjoint_variant = variant;
   } else if (op == 4 || op == 7) {
     if (variant < 0 || variant > 2) return fail(VAM_ERR_INVALID_ARG, "segment order must be 0, 1 or 2");

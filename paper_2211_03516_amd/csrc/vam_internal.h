@@ -111,6 +111,7 @@ struct vam_geometry {
   int* box_begin;                // [n_boxes + 1] segment offsets
   int* box_id;                   // [n_boxes] linear box index (x fastest)
   int box_cells;                 // largest rotated-box footprint in cells (LDS)
+  int64_t n_supp;                // most samples in any 4 x 4 x 3 block of lab unit cells
   // inverse ray map of the voxel-driven gather deposit, built on first use
   vam::BoxGrid cells;            // lab-frame unit cells
   int* cell_begin;               // [cells + 1] entry offsets

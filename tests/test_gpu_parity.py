@@ -226,7 +226,8 @@ def test_box_edges_agree():
         g.set_box_edge(edge)
         for fixed in (0, 1):
             g.set_fixed_kernels(fixed)
-            for dep in (vam.ADJ_BOX_FP64, vam.ADJ_BOX_AGG, vam.ADJ_BOX_SHARED):
+            for dep in (vam.ADJ_BOX_FP64, vam.ADJ_BOX_AGG, vam.ADJ_BOX_SHARED, vam.ADJ_BOX_INT_AGG,
+                        vam.ADJ_BOX_INT_SHARED, vam.ADJ_BOX_INT):
                 g.set_adjoint_variant(dep)
                 ef = relL2(g.forward(x).cpu().numpy(), Pref)
                 ea = relL2(g.back(y).cpu().numpy(), Dref)
@@ -247,7 +248,8 @@ def test_adjoint_variants_agree():
     ref = oracle.adjoint(oracle.Geometry(p), y.cpu().numpy().astype(np.float64))
     for variant in (vam.ADJ_SCATTER_DIRECT, vam.ADJ_SCATTER_AGGREGATED, vam.ADJ_SCATTER_FP64,
                     vam.ADJ_TUNED_FP32, vam.ADJ_TUNED_FP64, vam.ADJ_BOX_FP64, vam.ADJ_BOX_FP32,
-                    vam.ADJ_BOX_AGG, vam.ADJ_GATHER, vam.ADJ_BOX_SHARED, vam.ADJ_DEFAULT):
+                    vam.ADJ_BOX_AGG, vam.ADJ_GATHER, vam.ADJ_BOX_SHARED, vam.ADJ_BOX_INT_AGG,
+                    vam.ADJ_BOX_INT_SHARED, vam.ADJ_BOX_INT, vam.ADJ_DEFAULT):
         g.set_adjoint_variant(variant)
         say("adjoint variant", variant)
         assert relL2(g.back(y).cpu().numpy(), ref) <= 1e-5
@@ -262,11 +264,40 @@ def test_box_deposits_any_step(step):
     rng = synth.SplitMix64(14)
     y = rng.uniform(8 * 40 * 40).reshape(8, 40, 40)
     ref = oracle.adjoint(oracle.Geometry(p), y)
-    for variant in (vam.ADJ_BOX_AGG, vam.ADJ_BOX_SHARED):
+    for variant in (vam.ADJ_BOX_AGG, vam.ADJ_BOX_SHARED, vam.ADJ_BOX_INT_AGG, vam.ADJ_BOX_INT_SHARED):
         g.set_adjoint_variant(variant)
         e = relL2(g.back(to_dev(y)).cpu().numpy(), ref)
         say("step %.1f deposit %d rel-L2 %.3e" % (step, variant, e))
         assert e <= 1e-5
+    g.close()
+
+
+def test_integer_deposit_dynamic_range_and_nonfinite():
+    # fixed-point LDS sums: the scale follows each (box, angle)'s largest
+    # value, so projections spanning 12 orders of magnitude across angles
+    # and pixels keep FP32-level accuracy; a NaN makes its footprint NaN
+    p = c2_small(40, n_pupil=4, n_angles=6)
+    g = gpu_geom(p)
+    rng = synth.SplitMix64(16)
+    y = rng.uniform(6 * 40 * 40).reshape(6, 40, 40)
+    y *= 10.0 ** (-12 * rng.uniform(6 * 40 * 40).reshape(6, 40, 40) ** 4)
+    y[2] *= 1e6
+    y[4, ::2] *= -1.0
+    ref = oracle.adjoint(oracle.Geometry(p), y)
+    for variant in (vam.ADJ_BOX_INT_AGG, vam.ADJ_BOX_INT_SHARED, vam.ADJ_BOX_INT, vam.ADJ_BOX_AGG):
+        g.set_adjoint_variant(variant)
+        D = g.back(to_dev(y)).cpu().numpy()
+        e = relL2(D, ref)
+        # the angles without the 1e6 factor, on their own
+        y_small = y.copy()
+        y_small[2] = 0.0
+        e_small = relL2(g.back(to_dev(y_small)).cpu().numpy(), oracle.adjoint(oracle.Geometry(p), y_small))
+        say("variant %d: rel-L2 %.3e, without the large angle %.3e" % (variant, e, e_small))
+        assert e <= 1e-5 and e_small <= 1e-5
+        bad = y.copy()
+        bad[3, 20, 20] = float("nan")
+        Db = g.back(to_dev(bad)).cpu().numpy()
+        assert np.isnan(Db).any()
     g.close()
 
 
@@ -399,7 +430,8 @@ def test_c2_full_adjoint_identity(c2_full):
     scale = float(Ax.norm() * y.double().norm())
     res = {}
     for variant in (vam.ADJ_DEFAULT, vam.ADJ_BOX_AGG, vam.ADJ_BOX_FP32, vam.ADJ_TUNED_FP64,
-                    vam.ADJ_SCATTER_AGGREGATED, vam.ADJ_GATHER, vam.ADJ_BOX_SHARED):
+                    vam.ADJ_SCATTER_AGGREGATED, vam.ADJ_GATHER, vam.ADJ_BOX_SHARED, vam.ADJ_BOX_INT_AGG,
+                    vam.ADJ_BOX_INT_SHARED):
         g.set_adjoint_variant(variant)
         Aty = g.back(y).double()
         rhs = float((x.double() * Aty).sum())
@@ -412,6 +444,7 @@ def test_c2_full_adjoint_identity(c2_full):
     # the FP32 forward sums (~7000 terms per pixel) bound the agreement
     assert res[vam.ADJ_DEFAULT] <= 5e-7 and res[vam.ADJ_TUNED_FP64] <= 5e-7
     assert res[vam.ADJ_BOX_AGG] <= 5e-7 and res[vam.ADJ_GATHER] <= 5e-7 and res[vam.ADJ_BOX_SHARED] <= 5e-7
+    assert res[vam.ADJ_BOX_INT_AGG] <= 5e-7 and res[vam.ADJ_BOX_INT_SHARED] <= 5e-7
     assert max(res.values()) <= 5e-5
 
 
