@@ -617,8 +617,14 @@ __global__ __launch_bounds__(256) void k_forward_boxc(MarchParams P, BoxParams B
   }
 }
 
-// LDS adds of the deposit: FP64, or 32-bit integers in fixed point with the
-// workgroup's scale S (rounded to nearest).
+// LDS adds of the deposit: FP64, or 32-bit integers in fixed point (the
+// values already carry the workgroup's scale S and are rounded to the
+// nearest integer, halves upwards, by one v_cvt_rpi_i32_f32).
+__device__ inline int round_to_int(float v) {
+  int r;
+  asm("v_cvt_rpi_i32_f32 %0, %1" : "=v"(r) : "v"(v));
+  return r;
+}
 template <typename LT>
 __device__ inline void lds_add(LT* p, float v, float S);
 template <>
@@ -626,8 +632,8 @@ __device__ inline void lds_add<double>(double* p, float v, float) {
   atomicAdd(p, (double)v);
 }
 template <>
-__device__ inline void lds_add<int>(int* p, float v, float S) {
-  atomicAdd(p, (int)__builtin_rintf(v * S));
+__device__ inline void lds_add<int>(int* p, float v, float) {
+  atomicAdd(p, round_to_int(v));
 }
 
 // LT = int: the footprint is accumulated in 32-bit fixed point (gfx950 adds
@@ -693,6 +699,7 @@ __global__ __launch_bounds__(NT) void k_back_boxc(MarchParams P, BoxParams Bp, c
     const RayRec R = P.rays[r];
     const SegStart g = seg_start(P, R, cs.x, cs.y, f, sg.y);
     float e = R.cw * pv * __builtin_amdgcn_exp2f(P.nb * g.tb);
+    if (kInt) e *= S;  // sample weights in the fixed-point units
     float kf = 0.0f;
     unsigned cur = 0xffffffffu;
     float w[8] = {0, 0, 0, 0, 0, 0, 0, 0};
