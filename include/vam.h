@@ -234,12 +234,13 @@ vam_status vam_export_rays(vam_geometry_t h, double* out);
  *   op 6, order:    work order of the box kernels, bit 0 forward, bit 1
  *                   deposit: 0 = boxes fastest (all XCDs work on the same
  *                   angles), 1 = XCD-aware (each XCD walks a contiguous
- *                   range of boxes, angles fastest).  Default 0.
+ *                   range of boxes, angles fastest); see also op 8, 9.
  *   op 7, order:    as op 4, for the forward projection (default 0).
  *   op 8, 9:        work order of the deposit (8) or forward (9) box
- *                   kernels: 0 = boxes fastest, 1 = XCD-aware with all
- *                   angles of a box on one XCD, A >= 2 = XCD-aware with the
- *                   angles of a box in blocks of A (up to 4096).
+ *                   kernels: 0 = boxes fastest (forward default), 1 =
+ *                   XCD-aware with all angles of a box on one XCD, A >= 2 =
+ *                   XCD-aware with the angles of a box in blocks of A (up
+ *                   to 4096; deposit default 8).
  * FP64 accumulators are allocated on first use.  Errors:
  * VAM_ERR_BAD_HANDLE, VAM_ERR_INVALID_ARG for an unknown op or variant. */
 vam_status vam_set_variant(vam_geometry_t h, int32_t op, int32_t variant);

@@ -355,6 +355,7 @@ vam_status vam_setup_geometry(const vam_geometry_desc* desc, hipStream_t stream,
   h->fixed_kernels = 1;
   h->seg_order = 2;
   h->deposit_threads = 256;
+  h->xcd_deposit = 8;  // XCD-aware deposit order, angles in blocks of 8 (fastest measured)
   h->angles.resize(desc->n_angles);
   for (int a = 0; a < desc->n_angles; ++a)
     h->angles[a] = desc->angles_rad ? desc->angles_rad[a] : 2.0 * M_PI * a / desc->n_angles;
