@@ -128,6 +128,7 @@ def main():
     ap.add_argument("--deposit-threads", type=int, default=0)
     ap.add_argument("--work-order", type=int, default=-1, help="bit 0 forward, bit 1 deposit: XCD-aware")
     ap.add_argument("--angle-block", default="", help="deposit[,forward] angle blocks of the XCD-aware work order")
+    ap.add_argument("--forward-cache", type=int, default=-1, help="1/0: forward keeps the current cell in registers")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
@@ -172,6 +173,8 @@ def main():
         g.set_deposit_threads(args.deposit_threads)
     if args.work_order >= 0:
         g.set_work_order(args.work_order & 1, args.work_order >> 1)
+    if args.forward_cache >= 0:
+        g.set_forward_cache(args.forward_cache)
     if args.angle_block:
         ab = [int(v) for v in args.angle_block.split(",")]
         g.set_angle_blocks(deposit=ab[0], forward=ab[1] if len(ab) > 1 else None)

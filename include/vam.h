@@ -241,6 +241,9 @@ vam_status vam_export_rays(vam_geometry_t h, double* out);
  *                   XCD-aware with all angles of a box on one XCD, A >= 2 =
  *                   XCD-aware with the angles of a box in blocks of A (up
  *                   to 4096; deposit default 8).
+ *   op 10, cache:   1 = the fixed-footprint forward keeps the current
+ *                   cell's 8 corner values in registers and reads LDS only
+ *                   when a sample enters a new cell, 0 = reads every sample.
  * FP64 accumulators are allocated on first use.  Errors:
  * VAM_ERR_BAD_HANDLE, VAM_ERR_INVALID_ARG for an unknown op or variant. */
 vam_status vam_set_variant(vam_geometry_t h, int32_t op, int32_t variant);

@@ -271,6 +271,9 @@ class Geometry:
         if forward is not None:
             _check(lib().vam_set_variant(self.handle, 9, int(forward)))
 
+    def set_forward_cache(self, on):
+        _check(lib().vam_set_variant(self.handle, 10, int(bool(on))))
+
     def set_deposit_threads(self, n):
         _check(lib().vam_set_variant(self.handle, OP_DEPOSIT_THREADS, int(n)))
 

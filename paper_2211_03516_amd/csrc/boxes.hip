@@ -568,7 +568,10 @@ __device__ inline SegStart seg_start(const MarchParams& P, const RayRec& R, doub
   return g;
 }
 
-template <int B>
+// CACHE keeps the 8 corner values of the current cell in registers: at
+// steps of half a voxel about a third of the samples stay in the cell of the
+// previous one and then read nothing from LDS.
+template <int B, bool CACHE>
 __global__ __launch_bounds__(256) void k_forward_boxc(MarchParams P, BoxParams Bp, const float* __restrict__ vol,
                                                       float* __restrict__ part, int64_t n_rays, int smax) {
   constexpr int SY = Fixed<B>::WXY, SZ = SY * SY, NC = SZ * Fixed<B>::WZ;
@@ -595,6 +598,8 @@ __global__ __launch_bounds__(256) void k_forward_boxc(MarchParams P, BoxParams B
     const SegStart g = seg_start(P, R, cs.x, cs.y, f, sg.y);
     float S = 0.0f;
     float kf = (float)(cnt - 1);
+    unsigned cur = 0xffffffffu;
+    float v0 = 0.0f, v1 = 0.0f, v2 = 0.0f, v3 = 0.0f, v4 = 0.0f, v5 = 0.0f, v6 = 0.0f, v7 = 0.0f;
     for (int k = cnt - 1; k >= 0; --k, kf -= 1.0f) {
       const float x = __builtin_amdgcn_fmed3f(fmaf(kf, g.dx, g.px), 0.0f, hx);
       const float y = __builtin_amdgcn_fmed3f(fmaf(kf, g.dy, g.py), 0.0f, hy);
@@ -602,12 +607,23 @@ __global__ __launch_bounds__(256) void k_forward_boxc(MarchParams P, BoxParams B
       const float fx = __builtin_amdgcn_fractf(x), fy = __builtin_amdgcn_fractf(y),
                   fz = __builtin_amdgcn_fractf(z);
       const unsigned o = __umul24((unsigned)z, SZ) + __umul24((unsigned)y, SY) + (unsigned)x;
-      const float* p = sv + o;
-      const float* q = p + SZ;
-      const float c00 = fmaf(fx, p[1] - p[0], p[0]);
-      const float c01 = fmaf(fx, p[SY + 1] - p[SY], p[SY]);
-      const float c10 = fmaf(fx, q[1] - q[0], q[0]);
-      const float c11 = fmaf(fx, q[SY + 1] - q[SY], q[SY]);
+      if (!CACHE || o != cur) {
+        const float* p = sv + o;
+        const float* q = p + SZ;
+        v0 = p[0];
+        v1 = p[1];
+        v2 = p[SY];
+        v3 = p[SY + 1];
+        v4 = q[0];
+        v5 = q[1];
+        v6 = q[SY];
+        v7 = q[SY + 1];
+        cur = o;
+      }
+      const float c00 = fmaf(fx, v1 - v0, v0);
+      const float c01 = fmaf(fx, v3 - v2, v2);
+      const float c10 = fmaf(fx, v5 - v4, v4);
+      const float c11 = fmaf(fx, v7 - v6, v6);
       const float c0 = fmaf(fy, c01 - c00, c00);
       const float c1 = fmaf(fy, c11 - c10, c10);
       const float val = fmaf(fz, c1 - c0, c0);
@@ -1092,10 +1108,13 @@ static vam_status forward_box_t(vam_geometry* h, const MarchParams& P0, PT* proj
     Bw.segs = h->segs_fwd;
     if (h->n_boxes > 0 && fixed_edge(h->boxes.B) && h->fixed_kernels) {
       const dim3 grid = work_grid(h->n_boxes, nc, Bw.xcd);
-      switch (h->boxes.B) {
-        case 8: hipLaunchKernelGGL(k_forward_boxc<8>, grid, dim3(256), 0, s, P, Bw, h->vol_pad, h->seg_part, h->n_rays, smax); break;
-        case 12: hipLaunchKernelGGL(k_forward_boxc<12>, grid, dim3(256), 0, s, P, Bw, h->vol_pad, h->seg_part, h->n_rays, smax); break;
-        default: hipLaunchKernelGGL(k_forward_boxc<16>, grid, dim3(256), 0, s, P, Bw, h->vol_pad, h->seg_part, h->n_rays, smax); break;
+      switch (h->boxes.B * 2 + (h->fwd_cache ? 1 : 0)) {
+        case 16: hipLaunchKernelGGL((k_forward_boxc<8, false>), grid, dim3(256), 0, s, P, Bw, h->vol_pad, h->seg_part, h->n_rays, smax); break;
+        case 17: hipLaunchKernelGGL((k_forward_boxc<8, true>), grid, dim3(256), 0, s, P, Bw, h->vol_pad, h->seg_part, h->n_rays, smax); break;
+        case 24: hipLaunchKernelGGL((k_forward_boxc<12, false>), grid, dim3(256), 0, s, P, Bw, h->vol_pad, h->seg_part, h->n_rays, smax); break;
+        case 25: hipLaunchKernelGGL((k_forward_boxc<12, true>), grid, dim3(256), 0, s, P, Bw, h->vol_pad, h->seg_part, h->n_rays, smax); break;
+        case 32: hipLaunchKernelGGL((k_forward_boxc<16, false>), grid, dim3(256), 0, s, P, Bw, h->vol_pad, h->seg_part, h->n_rays, smax); break;
+        default: hipLaunchKernelGGL((k_forward_boxc<16, true>), grid, dim3(256), 0, s, P, Bw, h->vol_pad, h->seg_part, h->n_rays, smax); break;
       }
     } else if (h->n_boxes > 0) {
       static thread_local bool configured = false;

@@ -208,22 +208,36 @@ __global__ void k_sum_in_order(const double* part, int n, double scale, double* 
   *out = s * scale;
 }
 
-// Per-block column sums of g[p][c] (c < cp) over rows [b R, (b + 1) R).
+// Per-block column sums of g[p][c] (c < cp, cp a multiple of 8 and at most
+// 64) over rows [b R, (b + 1) R): each thread reads 8 channels of a row at
+// a time (16 B), then the block adds its threads' sums per channel in a
+// fixed order.
 __global__ __launch_bounds__(256) void k_colsum(const uint16_t* __restrict__ g, int64_t npix, int cp, int64_t rows,
                                                 float* __restrict__ part) {
-  __shared__ float sh[256];
-  const int per = 256 / cp;  // threads per channel
-  const int c = threadIdx.x % cp, j = threadIdx.x / cp;
+  __shared__ float sh[256 * 8];
+  const int chunks = cp >> 3;
+  const int per = 256 / chunks;  // rows in flight
+  const int c8 = threadIdx.x % chunks, j = threadIdx.x / chunks;
   const int64_t r0 = (int64_t)blockIdx.x * rows, r1 = min(r0 + rows, npix);
-  float s = 0.0f;
+  float acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   if (j < per)
-    for (int64_t p = r0 + j; p < r1; p += per) s += bf2f(g[p * cp + c]);
-  sh[threadIdx.x] = s;
+    for (int64_t p = r0 + j; p < r1; p += per) {
+      const uint4 v = *(const uint4*)(g + p * cp + c8 * 8);
+      const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        acc[2 * q] += __uint_as_float(w[q] << 16);
+        acc[2 * q + 1] += __uint_as_float(w[q] & 0xffff0000u);
+      }
+    }
+#pragma unroll
+  for (int q = 0; q < 8; ++q) sh[threadIdx.x * 8 + q] = acc[q];
   __syncthreads();
   if ((int)threadIdx.x < cp) {
+    const int c = threadIdx.x, cc = c >> 3, q = c & 7;
     float t = 0.0f;
-    for (int q = 0; q < per; ++q) t += sh[q * cp + threadIdx.x];
-    part[(int64_t)blockIdx.x * cp + threadIdx.x] = t;
+    for (int jj = 0; jj < per; ++jj) t += sh[(jj * chunks + cc) * 8 + q];
+    part[(int64_t)blockIdx.x * cp + c] = t;
   }
 }
 

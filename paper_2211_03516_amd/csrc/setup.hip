@@ -356,6 +356,7 @@ vam_status vam_setup_geometry(const vam_geometry_desc* desc, hipStream_t stream,
   h->seg_order = 2;
   h->deposit_threads = 256;
   h->xcd_deposit = 8;  // XCD-aware deposit order, angles in blocks of 8 (fastest measured)
+  h->fwd_cache = 0;
   h->angles.resize(desc->n_angles);
   for (int a = 0; a < desc->n_angles; ++a)
     h->angles[a] = desc->angles_rad ? desc->angles_rad[a] : 2.0 * M_PI * a / desc->n_angles;
@@ -496,6 +497,9 @@ vam_status vam_set_variant(vam_geometry_t h, int32_t op, int32_t variant) {
     if (variant < 0 || variant > 3) return fail(VAM_ERR_INVALID_ARG, "work order flags must be in [0, 3]");
     h->xcd_forward = variant & 1;
     h->xcd_deposit = (variant >> 1) & 1;
+  } else if (op == 10) {
+    if (variant < 0 || variant > 1) return fail(VAM_ERR_INVALID_ARG, "forward cell cache switch must be 0 or 1");
+    h->fwd_cache = variant;
   } else if (op == 8 || op == 9) {
     if (variant < 0 || variant > 4096) return fail(VAM_ERR_INVALID_ARG, "angle block must be in [0, 4096]");
     (op == 8 ? h->xcd_deposit : h->xcd_forward) = variant;

@@ -98,6 +98,7 @@ struct vam_geometry {
   int seg_order;                 // deposit order of segments inside a box (see build_boxes)
   int seg_order_fwd;             // forward order of segments inside a box
   int deposit_threads;           // workgroup size of the fixed-footprint deposit (256 or 512)
+  int fwd_cache;                 // 1: the fixed-footprint forward keeps the current cell's corners in registers
   int xcd_forward, xcd_deposit;  // 1: XCD-aware work order for the box kernels
   vam::BoxGrid boxes;
   int n_boxes;                   // boxes holding at least one segment

@@ -203,13 +203,15 @@ def test_forward_variants_agree():
     x = rng.uniform(48 ** 3).reshape(48, 48, 48)
     ref = oracle.forward(oracle.Geometry(p), x)
     for variant in (vam.FWD_PLAIN, vam.FWD_BOX, vam.FWD_TUNED, vam.FWD_DEFAULT):
-        g.set_forward_variant(variant)
-        P1 = g.forward(to_dev(x))
-        P2 = g.forward(to_dev(x))
-        assert torch.equal(P1, P2)              # every variant is deterministic
-        e = relL2(P1.cpu().numpy(), ref)
-        say("forward variant %d rel-L2 %.3e" % (variant, e))
-        assert e <= 1e-5
+        for cache in (0, 1):
+            g.set_forward_variant(variant)
+            g.set_forward_cache(cache)
+            P1 = g.forward(to_dev(x))
+            P2 = g.forward(to_dev(x))
+            assert torch.equal(P1, P2)              # every variant is deterministic
+            e = relL2(P1.cpu().numpy(), ref)
+            say("forward variant %d cache %d rel-L2 %.3e" % (variant, cache, e))
+            assert e <= 1e-5
     g.close()
 
 
@@ -226,6 +228,7 @@ def test_box_edges_agree():
         g.set_box_edge(edge)
         for fixed in (0, 1):
             g.set_fixed_kernels(fixed)
+            g.set_forward_cache(fixed)
             for dep in (vam.ADJ_BOX_FP64, vam.ADJ_BOX_AGG, vam.ADJ_BOX_SHARED, vam.ADJ_BOX_INT_AGG,
                         vam.ADJ_BOX_INT_SHARED, vam.ADJ_BOX_INT):
                 g.set_adjoint_variant(dep)
