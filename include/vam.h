@@ -124,9 +124,14 @@ vam_status vam_forward_project(vam_geometry_t h, const void* vol, vam_dtype vol_
 /* Dose deposit (Sec. 2.5), the exact transpose of vam_forward_project over
  * the same angle range: dose[nz][ny][nx] (FP32) receives
  * sum_a A_a^T proj[a - angle_begin].  accumulate != 0 adds to dose,
- * otherwise dose is overwritten.  Summation order is unspecified (results
- * may differ in the last bits between runs).  Errors as for
- * vam_forward_project. */
+ * otherwise dose is overwritten.  Rays whose projection value is exactly 0
+ * are skipped (they add nothing).  The default kernel sums each (box of the
+ * lab frame, angle) in 32-bit fixed point, scaled per box and angle so that
+ * no partial sum can overflow (rounding <= 2^-31 of a bound on the box's
+ * largest cell sum per add), then adds to an FP64 accumulator; the order of
+ * those FP64 additions is unspecified (results may differ in the last bits
+ * between runs).  A non-finite projection value makes the dose of the lab
+ * boxes its rays cross NaN.  Errors as for vam_forward_project. */
 vam_status vam_back_project(vam_geometry_t h, const void* proj, vam_dtype proj_t,
                             float* dose, int32_t accumulate,
                             int32_t angle_begin, int32_t angle_count,

@@ -153,6 +153,47 @@ __global__ void k_im2col(const uint16_t* __restrict__ x, int64_t npix, int H, in
   *(uint4*)(col + p * kp + k) = v;
 }
 
+// The same matrix transposed, colT[kc][p], for the weight gradient (whose
+// GEMM then reads both operands along the pixel sum).  Threads run along p
+// for one 8-channel chunk, so each of the 8 rows is written coalesced.
+__global__ void k_im2col_t(const uint16_t* __restrict__ x, int64_t npix, int H, int W, int cp, int kp,
+                           uint16_t* __restrict__ colT) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= npix * (kp >> 3)) return;
+  const int64_t j = i / npix, p = i - j * npix;
+  const int k = (int)j * 8;
+  uint4 v = make_uint4(0, 0, 0, 0);
+  if (k < 9 * cp) {
+    const int tap = k / cp, c = k - tap * cp;
+    const int w = (int)(p % W), h = (int)((p / W) % H);
+    const int hh = h + tap / 3 - 1, ww = w + tap % 3 - 1;
+    if (hh >= 0 && hh < H && ww >= 0 && ww < W) {
+      const int64_t q = p + (int64_t)(hh - h) * W + (ww - w);
+      v = *(const uint4*)(x + q * cp + c);
+    }
+  }
+  const uint32_t w4[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    colT[(int64_t)(k + 2 * q) * npix + p] = (uint16_t)(w4[q] & 0xffffu);
+    colT[(int64_t)(k + 2 * q + 1) * npix + p] = (uint16_t)(w4[q] >> 16);
+  }
+}
+
+// gT[c][p] = g[p][c] (c < cp, a multiple of 8).
+__global__ void k_transpose_g(const uint16_t* __restrict__ g, int64_t npix, int cp, uint16_t* __restrict__ gT) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= npix * (cp >> 3)) return;
+  const int64_t j = i / npix, p = i - j * npix;
+  const uint4 v = *(const uint4*)(g + p * cp + j * 8);
+  const uint32_t w4[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    gT[(j * 8 + 2 * q) * npix + p] = (uint16_t)(w4[q] & 0xffffu);
+    gT[(j * 8 + 2 * q + 1) * npix + p] = (uint16_t)(w4[q] >> 16);
+  }
+}
+
 // a0[p][c] = bf16(s_c x[img][c][h][w]) for c < 2, zero for 2 <= c < 8.
 __global__ void k_pack_input(const float* __restrict__ x, int64_t npix, int hw, float s0, float s1,
                              uint16_t* __restrict__ a0) {
@@ -586,20 +627,25 @@ vam_status vam_cnn_loss_grad(vam_cnn_t h, const float* x, const float* t, int32_
   const int ksplit = (int)(npix / splits);
   for (int l = L; l >= 1; --l) {
     const int i = l - 1;
-    // weight gradient: dW^T[kc][co] = sum_p col(a_{l-1})[p][kc] g_l[p][co]
-    CNN_TRY(im2col(h->act[i], npix, h->H, h->W, h->cinp[i], h->kp[i], h->col, s));
+    // weight gradient: dW^T[kc][co] = sum_p colT(a_{l-1})[kc][p] gT_l[co][p],
+    // both operands laid out along the pixel sum (gT in the free buffer)
+    hipLaunchKernelGGL(k_im2col_t, dim3(nblocks(npix * (h->kp[i] / 8), 256)), dim3(256), 0, s, h->act[i], npix,
+                       h->H, h->W, h->cinp[i], h->kp[i], h->col);
+    hipLaunchKernelGGL(k_transpose_g, dim3(nblocks(npix * (h->coutp[i] / 8), 256)), dim3(256), 0, s, gcur, npix,
+                       h->coutp[i], gnext);
+    VAM_HIP_TRY(hipGetLastError(), "launching the transposed im2col");
     GemmArgs a = {};
     a.A = h->col;
-    a.lda = h->kp[i];
-    a.B = gcur;
-    a.ldb = h->coutp[i];
+    a.lda = (int)npix;
+    a.B = gnext;
+    a.ldb = (int)npix;
     a.M = h->kp[i];
     a.N = h->cout[i];
     a.K = ksplit;
     a.C = h->part;
     a.ldc = h->coutp[i];
     a.split_stride = (int64_t)h->kp[i] * h->coutp[i];
-    CNN_TRY((gemm<true, true, EPI_PART_F32>(a, splits, s)));
+    CNN_TRY((gemm<false, false, EPI_PART_F32>(a, splits, s)));
     const int nw = h->cout[i] * 9 * h->cin[i];
     hipLaunchKernelGGL(k_wgrad_reduce, dim3(nblocks(nw, 256)), dim3(256), 0, s, h->part, splits, a.split_stride,
                        h->coutp[i], h->cinp[i], h->cin[i], h->cout[i], h->grad + h->woff[i]);

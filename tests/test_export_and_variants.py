@@ -60,3 +60,28 @@ def test_fin_stack_has_nine_fins_of_the_printed_period():
     np.testing.assert_allclose(np.diff(zs[rises[1:]]), 2.25, atol=voxel)
     falls = np.flatnonzero(np.diff(col.astype(int)) == -1) + 1
     np.testing.assert_allclose((falls[1:] - rises[1:]) * voxel, 1.0, atol=1.01 * voxel)
+
+
+def test_turned_voxel_support_fits_a_4x4x3_block_of_lab_cells():
+    # The fixed-point deposit bounds a voxel's sum by the samples in any
+    # 4 x 4 x 3 block of lab-frame unit cells: the voxel's support (open
+    # cube of half-width 1 in the volume frame) turned by any angle about z
+    # must overlap at most 4 unit cells along lab x and y and 3 along z.
+    import math
+    rng = synth.SplitMix64(90)
+    for _ in range(20000):
+        th = rng.uniform() * 2 * math.pi
+        c, s = math.cos(th), math.sin(th)
+        vx, vy, vz = (rng.uniform(3) - 0.5) * 200.0
+        # lab position of the voxel centre and the extent of the turned square
+        qx, qy = c * vx - s * vy, s * vx + c * vy
+        h = abs(c) + abs(s)
+        # unit cells overlapping the open intervals (q - h, q + h), (vz - 1, vz + 1)
+        def cells(lo, hi):
+            return math.ceil(hi) - math.floor(lo)
+        assert cells(qx - h, qx + h) <= 4 and cells(qy - h, qy + h) <= 4
+        assert cells(vz - 1.0, vz + 1.0) <= 3
+        # the corners of the turned square are within the bounding box
+        for dx, dy in ((-1, -1), (-1, 1), (1, -1), (1, 1)):
+            lx, ly = c * (vx + dx) - s * (vy + dy), s * (vx + dx) + c * (vy + dy)
+            assert qx - h - 1e-9 <= lx <= qx + h + 1e-9 and qy - h - 1e-9 <= ly <= qy + h + 1e-9
