@@ -114,6 +114,26 @@ def optimize(target, geom, proj=None, steps=50, lr=None, threshold=0.8, sharpnes
     return proj, hist
 
 
+def optimize_stored(target, geom, proj, steps, lr, dtype, threshold=0.8, sharpness=20.0):
+    """Projected gradient descent with the projections stored in `dtype`
+    (BF16 or FP16) and an FP32 master copy: every step deposits the stored
+    projections (the kernels accumulate in FP32/FP64), and the gradient of
+    the dose-threshold loss returns through the hand-written adjoint (the
+    forward projection, via `Dose`).  Returns (FP32 projections, per-step
+    losses)."""
+    torch_ = torch
+    master = proj.float().clone()
+    hist = []
+    for _ in range(steps):
+        stored = master.to(dtype).requires_grad_(True)
+        d = dose(stored, geom)
+        loss = ((torch_.sigmoid(sharpness * (d - threshold)) - target) ** 2).mean()
+        loss.backward()
+        master.sub_(lr * stored.grad.float()).clamp_(min=0.0)
+        hist.append(float(loss.detach()))
+    return master, hist
+
+
 def _first_step(target, geom, proj, threshold, sharpness, lr0=None, shrink=0.5, tries=12):
     """Armijo backtracking on a copy of the projections for the first step."""
     base = geom.optimize_step(target, proj.clone(), threshold=threshold, sharpness=sharpness, lr=0.0)
@@ -143,6 +163,8 @@ def _main(argv=None):
     ap.add_argument("--targets", type=int, default=8)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--seed0", type=int, default=0)
+    ap.add_argument("--storage", default="f32", choices=["f32", "bf16", "f16"],
+                    help="projection storage; bf16/f16 run the autograd loop with an FP32 master copy")
     a = ap.parse_args(argv)
     p = synth.workload(a.workload)
     g = Geometry(p)
@@ -157,15 +179,26 @@ def _main(argv=None):
         d0 = g.back(g0)
         e0, r0 = dose_error(d0, tt)
         t1 = time.perf_counter()
-        proj, hist = optimize(tt, g, proj=g0, steps=a.steps, check_every=max(1, a.steps // 5))
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t1
-        last = [h for h in hist if "dose_error" in h][-1]
-        print(json.dumps({"workload": a.workload, "target_seed": a.seed0 + i, "init_s": t_init,
-                          "dose_error_init": e0, "voxel_error_init": r0,
-                          "loss_first": hist[0]["loss"], "loss_last": hist[-1]["loss"],
-                          "dose_error_last": last["dose_error"], "voxel_error_last": last["voxel_error"],
-                          "steps": len(hist), "s_per_step": dt / len(hist)}), flush=True)
+        if a.storage == "f32":
+            proj, hist = optimize(tt, g, proj=g0, steps=a.steps, check_every=max(1, a.steps // 5))
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t1
+            last = [h for h in hist if "dose_error" in h][-1]
+            rec = {"loss_first": hist[0]["loss"], "loss_last": hist[-1]["loss"],
+                   "dose_error_last": last["dose_error"], "voxel_error_last": last["voxel_error"],
+                   "steps": len(hist)}
+        else:
+            lr = _first_step(tt, g, g0, 0.8, 20.0)
+            sdt = {"bf16": torch.bfloat16, "f16": torch.float16}[a.storage]
+            proj, losses = optimize_stored(tt, g, g0, a.steps, lr, sdt)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t1
+            e1, r1 = dose_error(g.back(proj.to(sdt)), tt)
+            rec = {"loss_first": losses[0], "loss_last": losses[-1], "dose_error_last": e1,
+                   "voxel_error_last": r1, "steps": len(losses)}
+        print(json.dumps({"workload": a.workload, "storage": a.storage, "target_seed": a.seed0 + i,
+                          "init_s": t_init, "dose_error_init": e0, "voxel_error_init": r0, **rec,
+                          "s_per_step": dt / rec["steps"]}), flush=True)
     g.close()
     return 0
 

@@ -125,3 +125,21 @@ def test_equalize_u8_matches_definition():
     assert np.array_equal(got[~ambiguous], ref[~ambiguous])
     assert np.all(np.abs(got[ambiguous].astype(int) - ref[ambiguous].astype(int)) <= 1)
     say("equalize: mean %.6f std %.6f clip %.6f, %d ambiguous" % (mean, sd, clip, int(ambiguous.sum())))
+
+
+def test_bf16_storage_optimisation_tracks_fp32():
+    # c3-style loop with projections stored in BF16 (FP32 master copy):
+    # same start, same step size, losses within a few percent of FP32
+    p = scaled(synth.workload("c1"), n_angles=30)
+    t, _ = synth.random_config1_target(64, 32.0, seed=6)
+    g = vam.Geometry(p)
+    tt = torch.from_numpy(t).to(DEV)
+    g0 = optim.plain_init(tt, g)
+    lr = 0.25 * optim._first_step(tt, g, g0, 0.8, 20.0)   # a step size that keeps descending
+    p32, h32 = optim.optimize(tt, g, proj=g0.clone(), steps=15, lr=lr)
+    p16, h16 = optim.optimize_stored(tt, g, g0.clone(), 15, lr, torch.bfloat16)
+    say("FP32 loss %.5f -> %.5f, BF16 storage %.5f -> %.5f" % (h32[0]["loss"], h32[-1]["loss"], h16[0], h16[-1]))
+    assert h32[-1]["loss"] < h32[0]["loss"] and h16[-1] < h16[0]
+    assert h16[0] == pytest.approx(h32[0]["loss"], rel=2e-2)
+    assert h16[-1] == pytest.approx(h32[-1]["loss"], rel=5e-2)
+    g.close()
