@@ -51,7 +51,7 @@ extern "C" {
 typedef enum {
   VAM_OK = 0,
   VAM_ERR_INVALID_ARG = -1,   /* bad descriptor, pointer, size or range    */
-  VAM_ERR_UNSUPPORTED = -2,   /* valid request this build does not handle  */
+  VAM_ERR_UNSUPPORTED = -2,   /* valid request the library does not handle */
   VAM_ERR_OUT_OF_MEMORY = -3, /* a device allocation failed                */
   VAM_ERR_HIP = -4,           /* a HIP runtime call or launch failed       */
   VAM_ERR_BAD_HANDLE = -5     /* NULL or destroyed geometry handle         */
