@@ -154,29 +154,46 @@ __global__ void k_im2col(const uint16_t* __restrict__ x, int64_t npix, int H, in
 }
 
 // The same matrix transposed, colT[kc][p], for the weight gradient (whose
-// GEMM then reads both operands along the pixel sum).  Threads run along p
-// for one 8-channel chunk, so each of the 8 rows is written coalesced.
-__global__ void k_im2col_t(const uint16_t* __restrict__ x, int64_t npix, int H, int W, int cp, int kp,
-                           uint16_t* __restrict__ colT) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= npix * (kp >> 3)) return;
-  const int64_t j = i / npix, p = i - j * npix;
-  const int k = (int)j * 8;
-  uint4 v = make_uint4(0, 0, 0, 0);
-  if (k < 9 * cp) {
-    const int tap = k / cp, c = k - tap * cp;
-    const int w = (int)(p % W), h = (int)((p / W) % H);
-    const int hh = h + tap / 3 - 1, ww = w + tap % 3 - 1;
-    if (hh >= 0 && hh < H && ww >= 0 && ww < W) {
-      const int64_t q = p + (int64_t)(hh - h) * W + (ww - w);
-      v = *(const uint4*)(x + q * cp + c);
+// GEMM then reads both operands along the pixel sum).  A workgroup moves a
+// tile of 64 pixels x 64 columns through LDS: 16-byte reads of 8 channels
+// of a pixel, 16-byte writes of 8 pixels of a column.
+__global__ __launch_bounds__(256) void k_im2col_t(const uint16_t* __restrict__ x, int64_t npix, int H, int W,
+                                                  int cp, int kp, uint16_t* __restrict__ colT) {
+  constexpr int TP = 64, TK = 64, LDP = TP + 8;
+  __shared__ __attribute__((aligned(16))) uint16_t tile[TK * LDP];
+  const int64_t p0 = (int64_t)blockIdx.x * TP;
+  const int k0 = blockIdx.y * TK;
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int h2 = 0; h2 < 2; ++h2) {
+    const int pl = (t >> 3) + 32 * h2, cl = (t & 7) * 8;
+    const int64_t p = p0 + pl;
+    const int k = k0 + cl;
+    uint4 v = make_uint4(0, 0, 0, 0);
+    if (p < npix && k < kp && k < 9 * cp) {
+      const int tap = k / cp, c = k - tap * cp;
+      const int w = (int)(p % W), h = (int)((p / W) % H);
+      const int hh = h + tap / 3 - 1, ww = w + tap % 3 - 1;
+      if (hh >= 0 && hh < H && ww >= 0 && ww < W) {
+        const int64_t q = p + (int64_t)(hh - h) * W + (ww - w);
+        v = *(const uint4*)(x + q * cp + c);
+      }
+    }
+    const uint32_t w4[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      tile[(cl + 2 * q) * LDP + pl] = (uint16_t)(w4[q] & 0xffffu);
+      tile[(cl + 2 * q + 1) * LDP + pl] = (uint16_t)(w4[q] >> 16);
     }
   }
-  const uint32_t w4[4] = {v.x, v.y, v.z, v.w};
+  __syncthreads();
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    colT[(int64_t)(k + 2 * q) * npix + p] = (uint16_t)(w4[q] & 0xffffu);
-    colT[(int64_t)(k + 2 * q + 1) * npix + p] = (uint16_t)(w4[q] >> 16);
+  for (int h2 = 0; h2 < 2; ++h2) {
+    const int row = (t >> 3) + 32 * h2, pc = (t & 7) * 8;
+    const int k = k0 + row;
+    const int64_t p = p0 + pc;
+    if (k < kp && p < npix)  // npix is a multiple of 32, so 8 pixels are in range together
+      *(uint4*)(colT + (int64_t)k * npix + p) = *(const uint4*)(tile + row * LDP + pc);
   }
 }
 
@@ -629,8 +646,8 @@ vam_status vam_cnn_loss_grad(vam_cnn_t h, const float* x, const float* t, int32_
     const int i = l - 1;
     // weight gradient: dW^T[kc][co] = sum_p colT(a_{l-1})[kc][p] gT_l[co][p],
     // both operands laid out along the pixel sum (gT in the free buffer)
-    hipLaunchKernelGGL(k_im2col_t, dim3(nblocks(npix * (h->kp[i] / 8), 256)), dim3(256), 0, s, h->act[i], npix,
-                       h->H, h->W, h->cinp[i], h->kp[i], h->col);
+    hipLaunchKernelGGL(k_im2col_t, dim3((unsigned)((npix + 63) / 64), (unsigned)((h->kp[i] + 63) / 64)), dim3(256), 0,
+                       s, h->act[i], npix, h->H, h->W, h->cinp[i], h->kp[i], h->col);
     hipLaunchKernelGGL(k_transpose_g, dim3(nblocks(npix * (h->coutp[i] / 8), 256)), dim3(256), 0, s, gcur, npix,
                        h->coutp[i], gnext);
     VAM_HIP_TRY(hipGetLastError(), "launching the transposed im2col");

@@ -42,3 +42,26 @@ def test_learned_start_beats_plain_start():
     assert s["reached"] == len(rows)
     assert s["mean_learned_steps"] < s["mean_plain_steps"]
     net.close()
+
+
+def test_fallback_to_the_plain_start():
+    # a network whose output is far from any useful start must not be used:
+    # the evaluation falls back to the filtered start and then follows the
+    # plain method
+    p = synth.workload("c5")
+    r = 0.5
+    p = synth.configs.scaled(p, nx=64, ny=64, nz=64, nu=64, nv=64, n_angles=60, r_outer=p["r_outer"] * r,
+                             r_inner=p["r_inner"] * r, focus=p["focus"] * r, pupil=p["pupil"] * r)
+    net = Cnn(3, 8, 64, 64, max_batch=16, in_scale=(1.0, 1.0))
+    bad = synth.cnninit.he_init(3, 8, seed=1, zero_last=False)
+    last = synth.cnninit.param_count(3, 8) - (1 * 9 * 8 + 1)
+    bad[last:] = -50.0                     # last layer: a large negative offset (dose < 0 everywhere)
+    net.set_params(bad)
+    rows = learned.evaluate(net, p, [5100, 5101], 8, synth.random_config2_target, 16, log=say)
+    for r_ in rows:
+        assert r_["fallback"]
+        assert r_["dose_error_learned_start"] > r_["dose_error_plain_start"]
+        # same start and step size as the plain run (the dose can differ in
+        # its last bits: the deposit's FP64 sums are not ordered)
+        assert r_["learned_steps"] <= r_["plain_steps"]
+    net.close()
