@@ -171,6 +171,25 @@ def test_rays_missing_the_vial():
     g2.close()
 
 
+def test_zero_inputs_and_single_pixel_dmd():
+    # all-zero volume / projections give exact zeros on every default path;
+    # a 1 x 1 DMD with one angle still matches the oracle
+    p = c2_small(24, n_pupil=4, n_angles=3)
+    g = gpu_geom(p)
+    assert float(g.forward(torch.zeros((24, 24, 24), device=DEV)).abs().max()) == 0.0
+    assert float(g.back(torch.zeros((3, 24, 24), device=DEV)).abs().max()) == 0.0
+    g.close()
+    p1 = dict(c2_small(16, n_pupil=4, n_angles=1), nu=1, nv=1)
+    g1 = gpu_geom(p1)
+    rng = synth.SplitMix64(17)
+    x = rng.uniform(16 ** 3).reshape(16, 16, 16)
+    og = oracle.Geometry(p1)
+    assert relL2(g1.forward(to_dev(x)).cpu().numpy(), oracle.forward(og, x)) <= 1e-5
+    y = np.array([[[0.7]]])
+    assert relL2(g1.back(to_dev(y)).cpu().numpy(), oracle.adjoint(og, y)) <= 1e-5
+    g1.close()
+
+
 # ---------------------------------------------------- API behaviour -------
 
 def test_angle_ranges_determinism_accumulate():
