@@ -143,3 +143,34 @@ def test_bf16_storage_optimisation_tracks_fp32():
     assert h16[0] == pytest.approx(h32[0]["loss"], rel=2e-2)
     assert h16[-1] == pytest.approx(h32[-1]["loss"], rel=5e-2)
     g.close()
+
+
+def test_paper_pipeline_fin_stack_hex13_export():
+    # the paper's chain at a small size: fin-stack target, 13-ray hexagonal
+    # pupil, plain filtered start, optimisation, 8-bit export
+    from oracle import export
+    n = 64
+    p = scaled(synth.workload("c5"), nx=n, ny=n, nz=n, nu=n, nv=n, n_angles=48, n_pupil=13,
+               pupil_xy=synth.pupil_hex13(), r_outer=30.0, r_inner=28.0,
+               focus=synth.workload("c5")["focus"] / 2, pupil=synth.workload("c5")["pupil"] / 2)
+    t = synth.fin_stack_target(n, 0.4).astype(np.float32)
+    assert t.sum() > 0
+    og = oracle.Geometry(p)
+    g = vam.Geometry(p)
+    # forward parity with the hex-13 pupil table
+    P = g.forward(torch.from_numpy(t).to(DEV)).cpu().numpy()
+    assert relL2(P, oracle.forward(og, t)) <= 1e-5
+    tt = torch.from_numpy(t).to(DEV)
+    g0 = optim.plain_init(tt, g)
+    e0, _ = vam.dose_error(g.back(g0), tt)
+    proj, hist = optim.optimize(tt, g, proj=g0.clone(), steps=20)
+    say("fin stack, hex-13 pupil: dose error %.4f -> %.4f" % (e0, hist[-1]["dose_error"]))
+    assert hist[-1]["dose_error"] < e0
+    q, (mean, sd, clip) = vam.equalize_u8(proj)
+    ref, (rmean, rsd, rclip) = export.equalize_u8(proj.double().cpu().numpy())
+    assert mean == pytest.approx(rmean, rel=1e-9) and clip == pytest.approx(rclip, rel=1e-9)
+    v = np.minimum(np.maximum(proj.double().cpu().numpy(), 0), clip) * (255.0 / clip)
+    tie = np.abs(v - np.floor(v) - 0.5) < 1e-9
+    assert np.array_equal(q.cpu().numpy()[~tie], ref[~tie])
+    assert int(q.min()) == 0 and int(q.max()) >= 128
+    g.close()
