@@ -5,7 +5,7 @@
 // the resin samples of every ray are cut into segments, one per lab-frame
 // box of B^3 voxels that they cross.  The deposit then runs one workgroup
 // per (box, angle): the box, rotated into the volume frame, covers a small
-// footprint of the padded grid (at most ~(B sqrt 2 + 3)^2 (B + 3) cells),
+// footprint of the padded grid (at most ~(B sqrt 2 + 3)^2 (B + 2) cells),
 // which the workgroup accumulates in LDS with LDS atomics while it marches
 // all segments of the box -- about 40 samples per voxel at the full-optics
 // workload, i.e. ~320 corner deposits per cell -- and then adds to the
@@ -29,7 +29,7 @@ constexpr int kMaxLdsBytes = 160 * 1024;  // LDS per CU on gfx950
 // y and B in z; the footprint adds the rounding margin and the +1 corner.
 static void footprint_bound(int B, int px, int py, int pz, int& wxy, int& wz) {
   wxy = std::min((int)std::floor(B * std::sqrt(2.0) + 3.02), std::max(px, py));
-  wz = std::min(B + 3, pz);
+  wz = std::min(B + 2, pz);
 }
 
 int max_box_edge(const vam_geometry* h) {
@@ -406,7 +406,13 @@ __device__ inline Foot footprint(const BoxParams& Bp, int box, double c, double 
   Foot f;
   range(gxmin, gxmax, Bp.px, Bp.wxy_max, f.X0, f.WX);
   range(gymin, gymax, Bp.py, Bp.wxy_max, f.Y0, f.WY);
-  range((double)(bz * G.B), (double)((bz + 1) * G.B), Bp.pz, Bp.wz_max, f.Z0, f.WZ);
+  // z does not turn and the boxes sit on whole cells: the box's samples have
+  // z in [bz B, (bz + 1) B) up to the FP32 rounding of their positions, so
+  // the footprint starts at bz B (a sample a rounding error below is clamped
+  // onto it) and ends one cell above the last corner
+  f.Z0 = min(max(bz * G.B, 0), Bp.pz - 2);
+  const int zhi = min(min((bz + 1) * G.B + 2, Bp.pz), f.Z0 + Bp.wz_max);
+  f.WZ = max(zhi, f.Z0 + 2) - f.Z0;
   return f;
 }
 
@@ -536,16 +542,18 @@ template <int B>
 struct Fixed;
 template <>
 struct Fixed<8> {
-  static constexpr int WXY = 14, WZ = 11;
+  static constexpr int WXY = 14, WZ = 10;
 };
 template <>
 struct Fixed<12> {
-  static constexpr int WXY = 19, WZ = 15;
+  static constexpr int WXY = 19, WZ = 14;
 };
 template <>
 struct Fixed<16> {
-  static constexpr int WXY = 25, WZ = 19;
+  static constexpr int WXY = 25, WZ = 18;
 };
+static_assert(Fixed<8>::WZ == 8 + 2 && Fixed<12>::WZ == 12 + 2 && Fixed<16>::WZ == 16 + 2,
+              "fixed footprints must match footprint_bound");
 
 struct SegStart {
   float px, py, pz;   // first sample, footprint-local cell coordinates
