@@ -725,7 +725,7 @@ __global__ __launch_bounds__(NT) void k_back_boxc(MarchParams P, BoxParams Bp, c
     float e = R.cw * pv * __builtin_amdgcn_exp2f(P.nb * g.tb);
     if (kInt) e *= S;  // sample weights in the fixed-point units
     float kf = 0.0f;
-    unsigned cur = 0xffffffffu;
+    const float kend = (float)cnt;  // exact: a segment has fewer than 2^24 samples
     float w[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     // AGG == 2: the cell whose corners w holds, starting at the first sample's
     int cx = 0, cy = 0, cz = 0;
@@ -736,7 +736,17 @@ __global__ __launch_bounds__(NT) void k_back_boxc(MarchParams P, BoxParams Bp, c
       cz = (int)__builtin_amdgcn_fmed3f(g.pz, 0.0f, hz);
       base = __umul24((unsigned)cz, SZ) + __umul24((unsigned)cy, SY) + (unsigned)cx;
     }
-    for (int k = 0; k < cnt; ++k, kf += 1.0f) {
+    // AGG == 1: byte offset in acc of the cell whose corners w holds, also
+    // starting at the first sample's (w is zero until its first add)
+    constexpr unsigned kL = sizeof(LT);
+    auto cell_bytes = [&](float x, float y, float z) {
+      return __umul24((unsigned)z, SZ * kL) + __umul24((unsigned)y, SY * kL) + (unsigned)x * kL;
+    };
+    unsigned cur = 0;
+    if (AGG == 1)
+      cur = cell_bytes(__builtin_amdgcn_fmed3f(g.px, 0.0f, hx), __builtin_amdgcn_fmed3f(g.py, 0.0f, hy),
+                       __builtin_amdgcn_fmed3f(g.pz, 0.0f, hz));
+    for (; kf < kend; kf += 1.0f) {
       const float x = __builtin_amdgcn_fmed3f(fmaf(kf, g.dx, g.px), 0.0f, hx);
       const float y = __builtin_amdgcn_fmed3f(fmaf(kf, g.dy, g.py), 0.0f, hy);
       const float z = __builtin_amdgcn_fmed3f(fmaf(kf, g.dz, g.pz), 0.0f, hz);
@@ -829,24 +839,31 @@ __global__ __launch_bounds__(NT) void k_back_boxc(MarchParams P, BoxParams Bp, c
 #pragma unroll
         for (int c = 0; c < 8; ++c) w[c] += q[c];
       } else if (AGG) {
-        if (o != cur) {
-          if (cur != 0xffffffffu) {
-            LT* p = acc + cur;
-            lds_add(p, w[0], S);
-            lds_add(p + 1, w[1], S);
-            lds_add(p + SY, w[2], S);
-            lds_add(p + SY + 1, w[3], S);
-            lds_add(p + SZ, w[4], S);
-            lds_add(p + SZ + 1, w[5], S);
-            lds_add(p + SZ + SY, w[6], S);
-            lds_add(p + SZ + SY + 1, w[7], S);
-          }
-          cur = o;
+        // The run's sums are only read inside the flush and restart through
+        // keep = 0, so the loop carries w and cur without copies between
+        // iterations.
+        const unsigned ob = cell_bytes(x, y, z);
+        const bool fl = ob != cur;
+        if (fl) {
+          LT* p = (LT*)((char*)acc + cur);
+          lds_add(p, w[0], S);
+          lds_add(p + 1, w[1], S);
+          lds_add(p + SY, w[2], S);
+          lds_add(p + SY + 1, w[3], S);
+          lds_add(p + SZ, w[4], S);
+          lds_add(p + SZ + 1, w[5], S);
+          lds_add(p + SZ + SY, w[6], S);
+          lds_add(p + SZ + SY + 1, w[7], S);
+        }
+        const float keep = fl ? 0.0f : 1.0f;
+        cur = ob;
+        // w[2j] += yz (1 - fx), w[2j+1] += yz fx, written so that every
+        // update accumulates into w itself
+        const float yz[4] = {y00, y01, y10, y11};
 #pragma unroll
-          for (int c = 0; c < 8; ++c) w[c] = q[c];
-        } else {
-#pragma unroll
-          for (int c = 0; c < 8; ++c) w[c] += q[c];
+        for (int j = 0; j < 4; ++j) {
+          w[2 * j] = fmaf(-yz[j], fx, fmaf(keep, w[2 * j], yz[j]));
+          w[2 * j + 1] = fmaf(yz[j], fx, keep * w[2 * j + 1]);
         }
       } else {
         LT* p = acc + o;
@@ -872,8 +889,8 @@ __global__ __launch_bounds__(NT) void k_back_boxc(MarchParams P, BoxParams Bp, c
       lds_add(p + SZ + SY, w[6], S);
       lds_add(p + SZ + SY + 1, w[7], S);
     }
-    if (AGG == 1 && cur != 0xffffffffu) {
-      LT* p = acc + cur;
+    if (AGG == 1 && cnt > 0) {
+      LT* p = (LT*)((char*)acc + cur);
       lds_add(p, w[0], S);
       lds_add(p + 1, w[1], S);
       lds_add(p + SY, w[2], S);
