@@ -124,7 +124,8 @@ def main():
     ap.add_argument("--forward-variant", type=int, default=0)
     ap.add_argument("--box-edge", type=int, default=0)
     ap.add_argument("--fixed", type=int, default=1)
-    ap.add_argument("--seg-order", type=int, default=-1)
+    ap.add_argument("--seg-order", type=int, default=-1, help="segment order of the deposit")
+    ap.add_argument("--seg-order-fwd", type=int, default=-1, help="segment order of the forward")
     ap.add_argument("--deposit-threads", type=int, default=0)
     ap.add_argument("--work-order", type=int, default=-1, help="bit 0 forward, bit 1 deposit: XCD-aware")
     ap.add_argument("--angle-block", default="", help="deposit[,forward] angle blocks of the XCD-aware work order")
@@ -169,6 +170,8 @@ def main():
     g.set_fixed_kernels(args.fixed)
     if args.seg_order >= 0:
         g.set_segment_order(args.seg_order)
+    if args.seg_order_fwd >= 0:
+        g.set_segment_order(args.seg_order_fwd, forward=True)
     if args.deposit_threads:
         g.set_deposit_threads(args.deposit_threads)
     if args.work_order >= 0:

@@ -233,7 +233,10 @@ vam_status vam_export_rays(vam_geometry_t h, double* out);
  *                   0 = always use the runtime-stride box kernels.
  *   op 4, order:    order of the segments inside a box for the deposit:
  *                   0 = by ray, 1 = by decreasing length, 2 = by pixel
- *                   parity class then ray (default); rebuilds the boxes.
+ *                   parity class (u mod 2, v mod 2) then ray, 3, 4 = by
+ *                   class (u mod m, v mod m), m = 3 (default), 4, then ray,
+ *                   5 = by a hash of the ray index, 6 = by pixel, then
+ *                   pupil sample; rebuilds the boxes.
  *   op 5, threads:  workgroup size of the fixed-footprint deposit, 256
  *                   (default) or 512.
  *   op 6, order:    work order of the box kernels, bit 0 forward, bit 1

@@ -262,7 +262,11 @@ vam_status build_boxes(vam_geometry* h, hipStream_t s) {
   //  0: by ray -- neighbouring lanes handle neighbouring pixels;
   //  1: by decreasing length -- lanes of a wave march similar lengths;
   //  2: by pixel parity class (u mod 2, v mod 2), then ray -- the lanes of
-  //     a wave handle pixels two apart, whose trilinear stencils are disjoint.
+  //     a wave handle pixels two apart, whose trilinear stencils are disjoint;
+  //  3, 4: the same with classes (u mod m, v mod m), m = 3, 4;
+  //  5: by a hash of the ray index (lanes at unrelated positions);
+  //  6: by pixel, then pupil sample -- the rays of one pixel, which meet at
+  //     the focus plane, go to neighbouring lanes.
   {
     std::vector<int4> hs(std::max<int64_t>(total, 1));
     e = hipMemcpy(hs.data(), h->segs, total * sizeof(int4), hipMemcpyDeviceToHost);
@@ -273,7 +277,17 @@ vam_status build_boxes(vam_geometry* h, hipStream_t s) {
         const int r = s.x;
         const int u = r % nu, v = (r / nu) % nv;
         if (order == 1) return ((int64_t)(0x7fff - s.z) << 32) | (uint32_t)r;
-        if (order == 2) return ((int64_t)(((v & 1) << 1) | (u & 1)) << 32) | (uint32_t)r;
+        if (order >= 2 && order <= 4) {
+          const int m = order;
+          return ((int64_t)((v % m) * m + (u % m)) << 32) | (uint32_t)r;
+        }
+        if (order == 6) return (int64_t)(r % (nu * nv)) * D.n_pupil + r / (nu * nv);
+        if (order == 5) {
+          uint64_t x = (uint64_t)r + 0x9e3779b97f4a7c15ull;  // SplitMix64 finaliser
+          x = (x ^ (x >> 30)) * 0xbf58476d1ce4e5b9ull;
+          x = (x ^ (x >> 27)) * 0x94d049bb133111ebull;
+          return (int64_t)((x ^ (x >> 31)) >> 1);
+        }
         return r;
       };
       for (size_t i = 0; i + 1 < begin.size(); ++i)

@@ -341,6 +341,31 @@ def test_work_orders_agree():
     g.close()
 
 
+def test_segment_orders_agree():
+    # the order of the segments inside a box only decides which lane marches
+    # which segment: the forward sums each segment and then the segments of
+    # a ray in rank order (same bits for every order), and the integer
+    # deposit adds each segment's runs exactly inside a workgroup; only the
+    # FP64 atomic adds of the workgroups into the dose have a free order,
+    # which can move a result by one FP32 rounding
+    p = c2_small(40, n_pupil=4, n_angles=10)
+    g = gpu_geom(p)
+    rng = synth.SplitMix64(16)
+    x = to_dev(rng.uniform(40 ** 3).reshape(40, 40, 40))
+    y = to_dev(rng.uniform(10 * 40 * 40).reshape(10, 40, 40))
+    P0, D0 = g.forward(x), g.back(y)
+    for order in range(7):
+        g.set_segment_order(order)
+        g.set_segment_order(order, forward=True)
+        P1, D1 = g.forward(x), g.back(y)
+        dd = float(((D1 - D0).abs() / D0.abs().clamp_min(1e-30)).max())
+        say("segment order %d: forward equal %s, deposit max rel diff %.2e" % (order, torch.equal(P0, P1), dd))
+        assert torch.equal(P0, P1) and dd <= 2.0 ** -23
+    with pytest.raises(vam.VamError):
+        g.set_segment_order(7)
+    g.close()
+
+
 def test_gather_deposit_angles_accumulate_and_order():
     # the voxel-driven gather against the oracle on an angle sub-range, with
     # accumulation into an existing dose, and bitwise repeatable
