@@ -237,7 +237,8 @@ vam_status vam_export_rays(vam_geometry_t h, double* out);
  *                   class (u mod m, v mod m), m = 3, 4, then ray, 5 = by a
  *                   hash of the ray index, 6 = by pixel, then pupil sample,
  *                   7, 8 = order 3, then each run of 1024 (7, default) or
- *                   2048 (8) segments by decreasing length; rebuilds the
+ *                   2048 (8) segments by decreasing length, 9 = by pupil
+ *                   sample, then pixel column, then row; rebuilds the
  *                   boxes.
  *   op 5, threads:  workgroup size of the fixed-footprint deposit, 256
  *                   (default) or 512.

@@ -270,7 +270,9 @@ vam_status build_boxes(vam_geometry* h, hipStream_t s) {
   //  7, 8: order 3, then each run of 1024 (7) or 2048 (8) consecutive
   //     segments by decreasing length, so that the 64 lanes of a wave march
   //     similar lengths and the four waves of a workgroup get equal shares
-  //     (the same runs on order 0 make the forward slower: 180 -> 187 ms).
+  //     (the same runs on order 0 make the forward slower: 180 -> 187 ms);
+  //  9: by pupil sample, then pixel column u, then row v -- neighbouring
+  //     lanes march rays one pixel apart in z, which does not turn.
   {
     std::vector<int4> hs(std::max<int64_t>(total, 1));
     e = hipMemcpy(hs.data(), h->segs, total * sizeof(int4), hipMemcpyDeviceToHost);
@@ -286,6 +288,7 @@ vam_status build_boxes(vam_geometry* h, hipStream_t s) {
           return ((int64_t)((v % m) * m + (u % m)) << 32) | (uint32_t)r;
         }
         if (order == 6) return (int64_t)(r % (nu * nv)) * D.n_pupil + r / (nu * nv);
+        if (order == 9) return ((int64_t)(r / (nu * nv)) * nu + u) * nv + v;
         if (order == 5) {
           uint64_t x = (uint64_t)r + 0x9e3779b97f4a7c15ull;  // SplitMix64 finaliser
           x = (x ^ (x >> 30)) * 0xbf58476d1ce4e5b9ull;

@@ -484,7 +484,7 @@ vam_status vam_set_variant(vam_geometry_t h, int32_t op, int32_t variant) {
     if (variant < 0 || variant > 13) return fail(VAM_ERR_INVALID_ARG, "unknown deposit variant %d", variant);
     h->adjoint_variant = variant;
   } else if (op == 4 || op == 7) {
-    if (variant < 0 || variant > 8) return fail(VAM_ERR_INVALID_ARG, "segment order must be in [0, 8]");
+    if (variant < 0 || variant > 9) return fail(VAM_ERR_INVALID_ARG, "segment order must be in [0, 9]");
     VAM_HIP_TRY(hipSetDevice(h->device), "hipSetDevice");
     VAM_HIP_TRY(hipDeviceSynchronize(), "synchronising before rebuilding boxes");
     free_boxes(h);
