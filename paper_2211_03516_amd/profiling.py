@@ -3,6 +3,7 @@
     python -m paper_2211_03516_amd.profiling stats <run_kernel_stats.csv> [--cmd "..."]
     python -m paper_2211_03516_amd.profiling counters <run_counter_collection.csv> [--cmd "..."]
     python -m paper_2211_03516_amd.profiling traffic <fetch.csv> <write.csv> --copy-mib N [--out f.json]
+    python -m paper_2211_03516_amd.profiling l2 <l2 counters.csv> <run_kernel_stats.csv> --copy-mib N --calls ...
 
 `stats` prints the per-kernel table (calls, average / total milliseconds,
 share of GPU time); `counters` prints per-kernel averages of each counter
@@ -87,11 +88,58 @@ def traffic(fetch_csv, write_csv, copy_mib, root, calls=None):
     return out
 
 
+def l2(counter_csv, stats_csv, copy_mib, calls=None, out=sys.stdout):
+    """L1 -> L2 traffic per operator pass of the main kernels from
+    TCP_TCC_READ_REQ_sum / TCP_TCC_WRITE_REQ_sum (bytes per request taken
+    from the largest copy kernel: a device copy of copy_mib MiB reads and
+    writes exactly that much), the L2 hit rate TCC_HIT / (TCC_HIT + TCC_MISS)
+    and the read rate over the pass time of a kernel trace (AverageNs x
+    dispatches per pass)."""
+    calls = calls or {}
+    rows = list(csv.DictReader(open(counter_csv)))
+    acc = collections.defaultdict(lambda: collections.defaultdict(float))
+    ndisp = collections.defaultdict(lambda: collections.defaultdict(int))
+    copy = collections.defaultdict(float)
+    for r in rows:
+        c, v = r["Counter_Name"], float(r["Counter_Value"])
+        if "copyBuffer" in r["Kernel_Name"]:
+            copy[c] = max(copy[c], v)
+        for name, pat in KERNELS.items():
+            if pat in r["Kernel_Name"]:
+                acc[name][c] += v
+                ndisp[name][c] += 1
+    nbytes = copy_mib * 1048576.0
+    rd = nbytes / copy["TCP_TCC_READ_REQ_sum"] if copy.get("TCP_TCC_READ_REQ_sum") else None
+    wr = nbytes / copy["TCP_TCC_WRITE_REQ_sum"] if copy.get("TCP_TCC_WRITE_REQ_sum") else None
+    avg_ms = {}
+    for r in csv.DictReader(open(stats_csv)):
+        for name, pat in KERNELS.items():
+            if pat in r["Name"]:
+                avg_ms[name] = float(r["AverageNs"]) / 1e6
+    out.write("# calibration (%g MiB copy): %.0f B per L1->L2 read request, %.0f B per write request\n"
+              % (copy_mib, rd or 0, wr or 0))
+    for name in KERNELS:
+        if name not in acc or rd is None or wr is None:
+            continue
+        c = calls.get(name, 1)
+        a = acc[name]
+        reads = a["TCP_TCC_READ_REQ_sum"] * rd / c
+        writes = a["TCP_TCC_WRITE_REQ_sum"] * wr / c
+        hits, miss = a["TCC_HIT_sum"], a["TCC_MISS_sum"]
+        per_pass = max(ndisp[name].values()) / c
+        ms = avg_ms.get(name, 0.0) * per_pass
+        rate = reads / (ms * 1e-3) / 1e12 if ms else 0.0
+        out.write("%-8s L2 reads %.0f GB, writes %.0f GB per pass; %.2f TB/s read over %.0f ms; "
+                  "L2 hit rate %.1f %%; requests %.3g\n"
+                  % (name, reads / 1e9, writes / 1e9, rate, ms, 100.0 * hits / max(hits + miss, 1.0),
+                     a["TCC_REQ_sum"] / c))
+
+
 def main(argv=None):
     import json
     import os
     ap = argparse.ArgumentParser()
-    ap.add_argument("what", choices=["stats", "counters", "traffic"])
+    ap.add_argument("what", choices=["stats", "counters", "traffic", "l2"])
     ap.add_argument("path")
     ap.add_argument("path2", nargs="?")
     ap.add_argument("--cmd", default=None, help="command that produced the CSV (written as a header)")
@@ -112,6 +160,10 @@ def main(argv=None):
         return
     if a.cmd:
         sys.stdout.write("# command: %s\n" % a.cmd)
+    if a.what == "l2":
+        calls = {k: int(v) for k, v in (kv.split("=") for kv in a.calls.split(",") if kv)}
+        l2(a.path, a.path2, a.copy_mib, calls)
+        return
     {"stats": stats, "counters": counters}[a.what](a.path)
 
 
