@@ -223,7 +223,12 @@ vam_status vam_export_rays(vam_geometry_t h, double* out);
  *                   with the footprint summed in 32-bit fixed point (the
  *                   scale of each box and angle bounds every partial sum
  *                   below 2^31; rounding <= 2^-31 of that bound per add; a
- *                   non-finite projection value makes its footprint NaN).
+ *                   non-finite projection value makes its footprint NaN),
+ *                   14 = as 11 with the x-neighbouring corners of a cell
+ *                   added as one exact 64-bit integer pair (same rounded
+ *                   values and sums as 11, half the LDS adds, twice the
+ *                   LDS per workgroup; edges 8, 12, 16 with fixed kernels,
+ *                   else as 8).
  *   op 2, tiling:   variant = lab-box edge in voxels, from 4 up to the
  *                   largest edge whose FP64 footprint fits in the 160 KiB
  *                   of LDS (19 for grids of 24^3 voxels and more); rebuilds

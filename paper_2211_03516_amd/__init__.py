@@ -36,6 +36,7 @@ ADJ_BOX_FP64, ADJ_BOX_FP32, ADJ_BOX_AGG = 6, 7, 8
 ADJ_GATHER = 9
 ADJ_BOX_SHARED = 10
 ADJ_BOX_INT_AGG, ADJ_BOX_INT_SHARED, ADJ_BOX_INT = 11, 12, 13
+ADJ_BOX_INT_PAIR = 14
 OP_BOX_EDGE, OP_FIXED_KERNELS, OP_SEG_ORDER, OP_DEPOSIT_THREADS, OP_WORK_ORDER = 2, 3, 4, 5, 6
 OP_SEG_ORDER_FWD = 7
 

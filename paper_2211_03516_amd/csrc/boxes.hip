@@ -15,6 +15,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 #include <vector>
 
 #include "vam_internal.h"
@@ -686,6 +687,18 @@ template <>
 __device__ inline void lds_add<int>(int* p, float v, float) {
   atomicAdd(p, round_to_int(v));
 }
+// Packed pairs: the 64-bit word of a cell holds the exact integer
+// hi * 2^32 + lo, the sum of the fixed-point deposits into corner x (lo) and
+// corner x + 1 (hi) of the lanes whose cell it is.  Both parts stay within
+// +-2^31, so the sign-extended low half of the word is the x corner's sum
+// and the rest, shifted down by 32, the x + 1 corner's.
+__device__ inline unsigned long long pack_pair(float lo_v, float hi_v) {
+  const int lo = round_to_int(lo_v), hi = round_to_int(hi_v);
+  return ((unsigned long long)(unsigned)(hi + (lo >> 31)) << 32) | (unsigned)lo;
+}
+__device__ inline void lds_add_pair(long long* p, float lo, float hi) {
+  atomicAdd((unsigned long long*)p, pack_pair(lo, hi));
+}
 
 // LT = int: the footprint is accumulated in 32-bit fixed point (gfx950 adds
 // 32-bit integers in LDS about twice as fast as FP64).  Overflow is ruled
@@ -703,9 +716,12 @@ __global__ __launch_bounds__(NT) void k_back_boxc(MarchParams P, BoxParams Bp, c
                                                   double* __restrict__ dose) {
   // slice pitch one word longer than a slice: the 32-bit deposit at edge 12
   // measured 3 % faster than with SY * SY (pitches SY * SY + 2 .. + 4 were
-  // slower again; the pitch decides which LDS banks the lanes' adds share)
-  constexpr int SY = Fixed<B>::WXY, SZ = SY * SY + 1, NC = SZ * Fixed<B>::WZ;
-  constexpr bool kInt = sizeof(LT) == 4;
+  // slower again; the pitch decides which LDS banks the lanes' adds share);
+  // packed pairs keep SY * SY so that four workgroups fit in the LDS
+  constexpr int SY = Fixed<B>::WXY, SZ = SY * SY + (sizeof(LT) == 8 ? 0 : 1), NC = SZ * Fixed<B>::WZ;
+  constexpr bool kInt = std::is_integral<LT>::value;      // fixed point
+  constexpr bool kPair = kInt && sizeof(LT) == 8;          // packed x pairs
+  static_assert(!kPair || AGG == 1, "packed pairs are built with run aggregation only");
   __shared__ LT acc[NC];
   __shared__ unsigned s_pvmax;
   __shared__ int s_bad;
@@ -788,7 +804,7 @@ __global__ __launch_bounds__(NT) void k_back_boxc(MarchParams P, BoxParams Bp, c
       const float y11 = z1 * fy, y10 = z1 - y11;
       const float q[8] = {y00 - y00 * fx, y00 * fx, y01 - y01 * fx, y01 * fx,
                           y10 - y10 * fx, y10 * fx, y11 - y11 * fx, y11 * fx};
-      if (AGG == 2) {
+      if constexpr (AGG == 2) {
         // Corner sharing: moving one cell along an axis keeps the four
         // corners on the far face, so only the four on the near face are
         // added to LDS; the kept sums shift to the near side and the far
@@ -868,7 +884,7 @@ __global__ __launch_bounds__(NT) void k_back_boxc(MarchParams P, BoxParams Bp, c
         }
 #pragma unroll
         for (int c = 0; c < 8; ++c) w[c] += q[c];
-      } else if (AGG) {
+      } else if constexpr (AGG == 1) {
         // The run's sums are only read inside the flush and restart through
         // keep = 0, so the loop carries w and cur without copies between
         // iterations.
@@ -876,14 +892,21 @@ __global__ __launch_bounds__(NT) void k_back_boxc(MarchParams P, BoxParams Bp, c
         const bool fl = ob != cur;
         if (fl) {
           LT* p = (LT*)((char*)acc + cur);
-          lds_add(p, w[0], S);
-          lds_add(p + 1, w[1], S);
-          lds_add(p + SY, w[2], S);
-          lds_add(p + SY + 1, w[3], S);
-          lds_add(p + SZ, w[4], S);
-          lds_add(p + SZ + 1, w[5], S);
-          lds_add(p + SZ + SY, w[6], S);
-          lds_add(p + SZ + SY + 1, w[7], S);
+          if constexpr (kPair) {
+            lds_add_pair(p, w[0], w[1]);
+            lds_add_pair(p + SY, w[2], w[3]);
+            lds_add_pair(p + SZ, w[4], w[5]);
+            lds_add_pair(p + SZ + SY, w[6], w[7]);
+          } else {
+            lds_add(p, w[0], S);
+            lds_add(p + 1, w[1], S);
+            lds_add(p + SY, w[2], S);
+            lds_add(p + SY + 1, w[3], S);
+            lds_add(p + SZ, w[4], S);
+            lds_add(p + SZ + 1, w[5], S);
+            lds_add(p + SZ + SY, w[6], S);
+            lds_add(p + SZ + SY + 1, w[7], S);
+          }
         }
         const float keep = fl ? 0.0f : 1.0f;
         cur = ob;
@@ -908,35 +931,58 @@ __global__ __launch_bounds__(NT) void k_back_boxc(MarchParams P, BoxParams Bp, c
       }
       e = fmaf(e, P.r_hi, e * P.r_lo);
     }
-    if (AGG == 2 && cnt > 0) {
-      LT* p = acc + base;
-      lds_add(p, w[0], S);
-      lds_add(p + 1, w[1], S);
-      lds_add(p + SY, w[2], S);
-      lds_add(p + SY + 1, w[3], S);
-      lds_add(p + SZ, w[4], S);
-      lds_add(p + SZ + 1, w[5], S);
-      lds_add(p + SZ + SY, w[6], S);
-      lds_add(p + SZ + SY + 1, w[7], S);
-    }
-    if (AGG == 1 && cnt > 0) {
-      LT* p = (LT*)((char*)acc + cur);
-      lds_add(p, w[0], S);
-      lds_add(p + 1, w[1], S);
-      lds_add(p + SY, w[2], S);
-      lds_add(p + SY + 1, w[3], S);
-      lds_add(p + SZ, w[4], S);
-      lds_add(p + SZ + 1, w[5], S);
-      lds_add(p + SZ + SY, w[6], S);
-      lds_add(p + SZ + SY + 1, w[7], S);
+    if constexpr (AGG == 2) {
+      if (cnt > 0) {
+        LT* p = acc + base;
+        lds_add(p, w[0], S);
+        lds_add(p + 1, w[1], S);
+        lds_add(p + SY, w[2], S);
+        lds_add(p + SY + 1, w[3], S);
+        lds_add(p + SZ, w[4], S);
+        lds_add(p + SZ + 1, w[5], S);
+        lds_add(p + SZ + SY, w[6], S);
+        lds_add(p + SZ + SY + 1, w[7], S);
+      }
+    } else if constexpr (kPair) {
+      if (cnt > 0) {
+        LT* p = (LT*)((char*)acc + cur);
+        lds_add_pair(p, w[0], w[1]);
+        lds_add_pair(p + SY, w[2], w[3]);
+        lds_add_pair(p + SZ, w[4], w[5]);
+        lds_add_pair(p + SZ + SY, w[6], w[7]);
+      }
+    } else if constexpr (AGG == 1) {
+      if (cnt > 0) {
+        LT* p = (LT*)((char*)acc + cur);
+        lds_add(p, w[0], S);
+        lds_add(p + 1, w[1], S);
+        lds_add(p + SY, w[2], S);
+        lds_add(p + SY + 1, w[3], S);
+        lds_add(p + SZ, w[4], S);
+        lds_add(p + SZ + 1, w[5], S);
+        lds_add(p + SZ + SY, w[6], S);
+        lds_add(p + SZ + SY + 1, w[7], S);
+      }
     }
   }
   __syncthreads();
   for (int i = threadIdx.x; i < NC; i += blockDim.x) {
-    const LT raw = acc[i];
-    if (raw == (LT)0 && !bad) continue;
+    LT raw = acc[i];
+    if (!kPair && raw == (LT)0 && !bad) continue;
     const int z = i / SZ, rem = i - z * SZ, y = rem / SY, x = rem - y * SY;
     if (x >= f.WX || y >= f.WY || z >= f.WZ) continue;
+    if constexpr (kPair) {
+      // this cell's sum: the low half of its own word plus the high half of
+      // the word of its x - 1 neighbour in the same row
+      const long long lo = (long long)(int)(unsigned)raw;
+      long long hi = 0;
+      if (x > 0) {
+        const long long u = acc[i - 1];
+        hi = (u - (long long)(int)(unsigned)u) >> 32;
+      }
+      raw = lo + hi;
+      if (raw == 0 && !bad) continue;
+    }
     const int64_t gi = ((int64_t)(f.Z0 + z) * Bp.py + (f.Y0 + y)) * Bp.px + (f.X0 + x);
     unsafeAtomicAdd(dose + gi, bad ? __builtin_nan("") : (double)raw * invS);
   }
@@ -1017,16 +1063,31 @@ static void launch_boxc_edge(vam_geometry* h, const MarchParams& P, const BoxPar
   }
 }
 
+template <typename PT>
+static void launch_boxc_pair(vam_geometry* h, const MarchParams& P, const BoxParams& Bp, const PT* proj, int na,
+                             hipStream_t s) {
+  switch (h->boxes.B) {
+    case 8: launch_boxc<8, PT, 1, long long>(h, P, Bp, proj, na, s); break;
+    case 12: launch_boxc<12, PT, 1, long long>(h, P, Bp, proj, na, s); break;
+    default: launch_boxc<16, PT, 1, long long>(h, P, Bp, proj, na, s); break;
+  }
+}
+
 // Deposit variants of the box kernels: 6, 8, 10 accumulate the footprint in
 // FP64, 13, 11, 12 in 32-bit fixed point, each without aggregation, with
-// cell-run aggregation and with corner sharing.  Edges without a
-// fixed-footprint kernel use the runtime-stride FP64 kernels.
+// cell-run aggregation and with corner sharing; 14 in fixed point packed in
+// 64-bit x pairs, with run aggregation.  Edges without a fixed-footprint
+// kernel use the runtime-stride FP64 kernels.
 template <typename PT>
 static void launch_box_t(vam_geometry* h, const MarchParams& P, const PT* proj, int na, int variant,
                          hipStream_t s) {
   const BoxParams Bp = box_params(h);
   const bool fixed = fixed_edge(h->boxes.B) && h->fixed_kernels;
-  const int agg = (variant == 10 || variant == 12) ? 2 : (variant == 8 || variant == 11) ? 1 : 0;
+  const int agg = (variant == 10 || variant == 12) ? 2 : (variant == 8 || variant == 11 || variant == 14) ? 1 : 0;
+  if (fixed && variant == 14) {
+    launch_boxc_pair<PT>(h, P, Bp, proj, na, s);
+    return;
+  }
   if (fixed && (variant == 6 || variant == 8 || variant == 10)) {
     launch_boxc_edge<PT, double>(h, P, Bp, proj, na, agg, s);
     return;

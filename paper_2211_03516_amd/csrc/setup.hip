@@ -481,7 +481,7 @@ vam_status vam_set_variant(vam_geometry_t h, int32_t op, int32_t variant) {
     if (variant < 0 || variant > 3) return fail(VAM_ERR_INVALID_ARG, "unknown forward variant %d", variant);
     h->forward_variant = variant;
   } else if (op == 1) {
-    if (variant < 0 || variant > 13) return fail(VAM_ERR_INVALID_ARG, "unknown deposit variant %d", variant);
+    if (variant < 0 || variant > 14) return fail(VAM_ERR_INVALID_ARG, "unknown deposit variant %d", variant);
     h->adjoint_variant = variant;
   } else if (op == 4 || op == 7) {
     if (variant < 0 || variant > 9) return fail(VAM_ERR_INVALID_ARG, "segment order must be in [0, 9]");

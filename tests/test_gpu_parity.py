@@ -271,7 +271,7 @@ def test_adjoint_variants_agree():
     for variant in (vam.ADJ_SCATTER_DIRECT, vam.ADJ_SCATTER_AGGREGATED, vam.ADJ_SCATTER_FP64,
                     vam.ADJ_TUNED_FP32, vam.ADJ_TUNED_FP64, vam.ADJ_BOX_FP64, vam.ADJ_BOX_FP32,
                     vam.ADJ_BOX_AGG, vam.ADJ_GATHER, vam.ADJ_BOX_SHARED, vam.ADJ_BOX_INT_AGG,
-                    vam.ADJ_BOX_INT_SHARED, vam.ADJ_BOX_INT, vam.ADJ_DEFAULT):
+                    vam.ADJ_BOX_INT_SHARED, vam.ADJ_BOX_INT, vam.ADJ_BOX_INT_PAIR, vam.ADJ_DEFAULT):
         g.set_adjoint_variant(variant)
         say("adjoint variant", variant)
         assert relL2(g.back(y).cpu().numpy(), ref) <= 1e-5
@@ -286,7 +286,8 @@ def test_box_deposits_any_step(step):
     rng = synth.SplitMix64(14)
     y = rng.uniform(8 * 40 * 40).reshape(8, 40, 40)
     ref = oracle.adjoint(oracle.Geometry(p), y)
-    for variant in (vam.ADJ_BOX_AGG, vam.ADJ_BOX_SHARED, vam.ADJ_BOX_INT_AGG, vam.ADJ_BOX_INT_SHARED):
+    for variant in (vam.ADJ_BOX_AGG, vam.ADJ_BOX_SHARED, vam.ADJ_BOX_INT_AGG, vam.ADJ_BOX_INT_SHARED,
+                    vam.ADJ_BOX_INT_PAIR):
         g.set_adjoint_variant(variant)
         e = relL2(g.back(to_dev(y)).cpu().numpy(), ref)
         say("step %.1f deposit %d rel-L2 %.3e" % (step, variant, e))
@@ -306,7 +307,8 @@ def test_integer_deposit_dynamic_range_and_nonfinite():
     y[2] *= 1e6
     y[4, ::2] *= -1.0
     ref = oracle.adjoint(oracle.Geometry(p), y)
-    for variant in (vam.ADJ_BOX_INT_AGG, vam.ADJ_BOX_INT_SHARED, vam.ADJ_BOX_INT, vam.ADJ_BOX_AGG):
+    for variant in (vam.ADJ_BOX_INT_AGG, vam.ADJ_BOX_INT_SHARED, vam.ADJ_BOX_INT, vam.ADJ_BOX_INT_PAIR,
+                    vam.ADJ_BOX_AGG):
         g.set_adjoint_variant(variant)
         D = g.back(to_dev(y)).cpu().numpy()
         e = relL2(D, ref)
@@ -321,6 +323,32 @@ def test_integer_deposit_dynamic_range_and_nonfinite():
         Db = g.back(to_dev(bad)).cpu().numpy()
         assert np.isnan(Db).any()
     g.close()
+
+
+def test_packed_pair_deposit_matches_32_bit_sums():
+    # variant 14 adds the x-neighbouring corners of a cell as one exact
+    # 64-bit pair: the same rounded values and integer sums as variant 11,
+    # so the two agree up to the free order of the FP64 atomic adds of the
+    # workgroups into the dose; signed inputs exercise the sign handling of
+    # the pair (a negative x corner borrows from the x + 1 half)
+    p = c2_small(40, n_pupil=4, n_angles=10)
+    rng = synth.SplitMix64(17)
+    y_pos = rng.uniform(10 * 40 * 40).reshape(10, 40, 40)
+    y_sgn = 2.0 * rng.uniform(10 * 40 * 40).reshape(10, 40, 40) - 1.0
+    for edge in (8, 12, 16):
+        g = gpu_geom(p)
+        g.set_box_edge(edge)
+        for y in (y_pos, y_sgn):
+            yd = to_dev(y)
+            g.set_adjoint_variant(vam.ADJ_BOX_INT_AGG)
+            D32 = g.back(yd)
+            g.set_adjoint_variant(vam.ADJ_BOX_INT_PAIR)
+            D64 = g.back(yd)
+            dd = float(((D64 - D32).abs() / D32.abs().clamp_min(1e-30)).max())
+            e = relL2(D64.cpu().numpy(), oracle.adjoint(oracle.Geometry(p), y))
+            say("edge %d: pair vs 32-bit max rel diff %.2e, rel-L2 vs oracle %.3e" % (edge, dd, e))
+            assert dd <= 2.0 ** -23 and e <= 1e-5
+        g.close()
 
 
 def test_work_orders_agree():
