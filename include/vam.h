@@ -241,10 +241,12 @@ vam_status vam_export_rays(vam_geometry_t h, double* out);
  *                   parity class (u mod 2, v mod 2) then ray, 3, 4 = by
  *                   class (u mod m, v mod m), m = 3, 4, then ray, 5 = by a
  *                   hash of the ray index, 6 = by pixel, then pupil sample,
- *                   7, 8 = order 3, then each run of 1024 (7, default) or
- *                   2048 (8) segments by decreasing length, 9 = by pupil
- *                   sample, then pixel column, then row; rebuilds the
- *                   boxes.
+ *                   7, 8 = order 3, then each run of 1024 (7) or 2048 (8)
+ *                   segments by decreasing length, 9 = by pupil sample,
+ *                   then pixel column, then row, 10 = by class (u mod 3,
+ *                   v mod 2), then ray, 11, 12, 13 = order 10, then each
+ *                   run of 1024 (11, default), 512 (12) or 2048 (13)
+ *                   segments by decreasing length; rebuilds the boxes.
  *   op 5, threads:  workgroup size of the fixed-footprint deposit, 256
  *                   (default) or 512.
  *   op 6, order:    work order of the box kernels, bit 0 forward, bit 1

@@ -273,7 +273,11 @@ vam_status build_boxes(vam_geometry* h, hipStream_t s) {
   //     similar lengths and the four waves of a workgroup get equal shares
   //     (the same runs on order 0 make the forward slower: 180 -> 187 ms);
   //  9: by pupil sample, then pixel column u, then row v -- neighbouring
-  //     lanes march rays one pixel apart in z, which does not turn.
+  //     lanes march rays one pixel apart in z, which does not turn;
+  //  10: by class (u mod 3, v mod 2), then ray (lanes three pixels apart
+  //     along a row, rows two apart);
+  //  11, 12, 13: order 10, then each run of 1024 (11), 512 (12) or 2048
+  //     (13) consecutive segments by decreasing length.
   {
     std::vector<int4> hs(std::max<int64_t>(total, 1));
     e = hipMemcpy(hs.data(), h->segs, total * sizeof(int4), hipMemcpyDeviceToHost);
@@ -290,6 +294,7 @@ vam_status build_boxes(vam_geometry* h, hipStream_t s) {
         }
         if (order == 6) return (int64_t)(r % (nu * nv)) * D.n_pupil + r / (nu * nv);
         if (order == 9) return ((int64_t)(r / (nu * nv)) * nu + u) * nv + v;
+        if (order == 10) return ((int64_t)((v % 2) * 3 + (u % 3)) << 32) | (uint32_t)r;
         if (order == 5) {
           uint64_t x = (uint64_t)r + 0x9e3779b97f4a7c15ull;  // SplitMix64 finaliser
           x = (x ^ (x >> 30)) * 0xbf58476d1ce4e5b9ull;
@@ -298,8 +303,11 @@ vam_status build_boxes(vam_geometry* h, hipStream_t s) {
         }
         return r;
       };
-      const int korder = (order == 7 || order == 8) ? 3 : order;
-      const int run = order == 7 ? 1024 : order == 8 ? 2048 : 0;
+      const int korder = (order == 7 || order == 8) ? 3 : (order >= 11 && order <= 13) ? 10 : order;
+      const int run = (order == 7 || order == 11)   ? 1024
+                      : (order == 8 || order == 13) ? 2048
+                      : order == 12                 ? 512
+                                                    : 0;
       for (size_t i = 0; i + 1 < begin.size(); ++i) {
         std::sort(hs.begin() + begin[i], hs.begin() + begin[i + 1],
                   [&](const int4& x, const int4& y) { return key(x, korder) < key(y, korder); });

@@ -353,7 +353,7 @@ vam_status vam_setup_geometry(const vam_geometry_desc* desc, hipStream_t stream,
   h->desc = *desc;
   h->adjoint_variant = 0;
   h->fixed_kernels = 1;
-  h->seg_order = 7;
+  h->seg_order = 11;
   h->deposit_threads = 256;
   h->xcd_deposit = 8;  // XCD-aware deposit order, angles in blocks of 8 (fastest measured)
   h->fwd_cache = 0;
@@ -484,7 +484,7 @@ vam_status vam_set_variant(vam_geometry_t h, int32_t op, int32_t variant) {
     if (variant < 0 || variant > 14) return fail(VAM_ERR_INVALID_ARG, "unknown deposit variant %d", variant);
     h->adjoint_variant = variant;
   } else if (op == 4 || op == 7) {
-    if (variant < 0 || variant > 9) return fail(VAM_ERR_INVALID_ARG, "segment order must be in [0, 9]");
+    if (variant < 0 || variant > 13) return fail(VAM_ERR_INVALID_ARG, "segment order must be in [0, 13]");
     VAM_HIP_TRY(hipSetDevice(h->device), "hipSetDevice");
     VAM_HIP_TRY(hipDeviceSynchronize(), "synchronising before rebuilding boxes");
     free_boxes(h);

@@ -382,7 +382,7 @@ def test_segment_orders_agree():
     x = to_dev(rng.uniform(40 ** 3).reshape(40, 40, 40))
     y = to_dev(rng.uniform(10 * 40 * 40).reshape(10, 40, 40))
     P0, D0 = g.forward(x), g.back(y)
-    for order in range(10):
+    for order in range(14):
         g.set_segment_order(order)
         g.set_segment_order(order, forward=True)
         P1, D1 = g.forward(x), g.back(y)
@@ -390,7 +390,7 @@ def test_segment_orders_agree():
         say("segment order %d: forward equal %s, deposit max rel diff %.2e" % (order, torch.equal(P0, P1), dd))
         assert torch.equal(P0, P1) and dd <= 2.0 ** -23
     with pytest.raises(vam.VamError):
-        g.set_segment_order(10)
+        g.set_segment_order(14)
     g.close()
 
 
