@@ -269,8 +269,10 @@ vam_status build_boxes(vam_geometry* h, hipStream_t s) {
   //  6: by pixel, then pupil sample -- the rays of one pixel, which meet at
   //     the focus plane, go to neighbouring lanes;
   //  7, 8: order 3, then each run of 1024 (7) or 2048 (8) consecutive
-  //     segments by decreasing length, so that the 64 lanes of a wave march
-  //     similar lengths and the four waves of a workgroup get equal shares
+  //     segments by decreasing length in steps of two samples (a stable sort:
+  //     equal steps keep their class order; exact lengths measured 1.5 %
+  //     slower), so that the 64 lanes of a wave march similar lengths and
+  //     the four waves of a workgroup get equal shares
   //     (the same runs on order 0 make the forward slower: 180 -> 187 ms);
   //  9: by pupil sample, then pixel column u, then row v -- neighbouring
   //     lanes march rays one pixel apart in z, which does not turn;
@@ -313,7 +315,7 @@ vam_status build_boxes(vam_geometry* h, hipStream_t s) {
                   [&](const int4& x, const int4& y) { return key(x, korder) < key(y, korder); });
         for (int64_t g = begin[i]; run && g < begin[i + 1]; g += run)
           std::stable_sort(hs.begin() + g, hs.begin() + std::min<int64_t>(g + run, begin[i + 1]),
-                           [](const int4& x, const int4& y) { return x.z > y.z; });
+                           [](const int4& x, const int4& y) { return (x.z >> 1) > (y.z >> 1); });
       }
     };
     e = hipMalloc(&h->segs_fwd, std::max<int64_t>(total, 1) * sizeof(int4));
