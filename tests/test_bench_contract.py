@@ -1,0 +1,40 @@
+"""Host-side parts of the benchmark contract: the multi-GPU refusal, the
+secondary metric read from the committed learned-initialiser run and the
+traffic figure's guard on the kernel sources."""
+import json
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, cwd=ROOT, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr or "single MI355X" in r.stderr
+
+
+def test_learned_vs_plain_comes_from_the_committed_run():
+    d = bench.learned_vs_plain()
+    assert d is not None and d["source"] == "profiles/learned_c5.txt"
+    assert d["command"].startswith("python -u -m paper_2211_03516_amd.learned")
+    assert 0 < d["learned_steps"] <= d["plain_steps"] and d["learned_s"] > 0 and d["plain_s"] > 0
+    # the summary line in the file is the one reported
+    summary = [json.loads(l) for l in open(os.path.join(ROOT, "profiles", "learned_c5.txt"))
+               if '"phase": "summary"' in l]
+    assert len(summary) == 1 and summary[0]["targets"] == d["targets"]
+
+
+def test_traffic_only_for_the_profiled_sources(monkeypatch):
+    t = json.load(open(os.path.join(ROOT, "profiles", "traffic_c2.json")))
+    if t["source_sha256"] == bench.kernel_source_hash():
+        got = bench.load_traffic("deposit")
+        assert got == t["deposit"]["fetch_bytes"] + t["deposit"]["write_bytes"]
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: "0" * 64)
+    assert bench.load_traffic("deposit") is None
