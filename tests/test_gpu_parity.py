@@ -100,6 +100,37 @@ def _parity_case(p, vol, proj_in, tol=1e-5):
     return g, og, Pg, Po
 
 
+@pytest.mark.parametrize("m", [1, 2])
+def test_mass_conservation_and_adjoint_of_ones(m):
+    # closed forms, no oracle: telecentric chief rays on the voxel lattice,
+    # no walls, alpha = 0, step 1/m, quarter turns.  The samples of a unit
+    # tent at spacing 1/m sum to m, so each angle's projection sums to the
+    # volume's sum, and the deposit of a projection of ones is the number of
+    # angles at every voxel 2 voxels inside the resin (zero outside it);
+    # 40^3 spans several lab boxes.
+    n, R = 40, 19.5
+    p = dict(nx=n, ny=n, nz=n, nu=n, nv=n, pitch_u=1.0, pitch_v=1.0, n_angles=4,
+             angles=np.array([0.0, 0.5, 1.0, 1.5]) * math.pi, projector=0, focus=0.0, pupil=0.0,
+             n_pupil=1, pupil_xy=None, flags=0, r_outer=R, r_inner=R, n_air=1.0, n_glass=1.47,
+             n_resin=1.49, alpha=0.0, step=1.0 / m)
+    g = gpu_geom(p)
+    z, y, x = np.meshgrid(*(np.arange(n) - (n - 1) / 2,) * 3, indexing="ij")
+    rho = np.hypot(x, y)
+    rng = synth.SplitMix64(21 + m)
+    vol = rng.uniform(n ** 3).reshape(n, n, n)
+    vol[rho > R - 2] = 0.0
+    P = g.forward(to_dev(vol)).double().cpu().numpy()
+    sums = P.reshape(4, -1).sum(axis=1) / vol.sum()
+    D = g.back(to_dev(np.ones((4, n, n)))).double().cpu().numpy()
+    inside = rho < R - 2
+    say("m %d: projection sums / volume sum %s; deposit of ones inside: %.7f .. %.7f"
+        % (m, np.array2string(sums, precision=8), D[inside].min(), D[inside].max()))
+    assert np.all(np.abs(sums - 1.0) <= 1e-6)
+    np.testing.assert_allclose(D[inside], 4.0, rtol=1e-6)
+    assert np.all(D[rho > R + 1.5] == 0.0)
+    g.close()
+
+
 def test_c1_full_forward_and_adjoint():
     p = synth.workload("c1")
     t, _ = synth.random_config1_target(64, 32.0, seed=0)

@@ -277,6 +277,25 @@ def test_mass_conservation_quarter_turns(m):
         assert P[a].sum() == pytest.approx(vol.sum(), rel=1e-12)
 
 
+@pytest.mark.parametrize("m", [1, 2])
+def test_adjoint_of_ones_is_the_angle_count(m):
+    """Transpose of the pin above, voxel by voxel: with pixel centres on the
+    voxel lattice and samples every 1/m along the ray, the tent weights of
+    one angle's samples around any voxel add up to exactly 1 (one in each
+    axis), so depositing a projection of ones gives n_angles at every voxel
+    whose stencil samples all lie in the resin."""
+    n = 20
+    p = _geom(nx=n, ny=n, nz=n, nu=n, nv=n, r_outer=9.5, r_inner=9.5,
+              step=1.0 / m, n_angles=4, angles=np.array([0, 0.5, 1.0, 1.5]) * math.pi)
+    D = oracle.adjoint(oracle.Geometry(p), np.ones((4, n, n)))
+    z, y, x = np.meshgrid(*(np.arange(n) - (n - 1) / 2,) * 3, indexing="ij")
+    inside = np.hypot(x, y) < 9.5 - 2
+    assert inside.sum() > 1000
+    np.testing.assert_allclose(D[inside], 4.0, rtol=1e-12)
+    # and outside the resin nothing is deposited
+    assert np.all(D[np.hypot(x, y) > 9.5 + 1.5] == 0.0)
+
+
 def test_mass_conservation_fails_off_lattice():
     """Control: with a step that is not 1/m, mass is not conserved to 1e-12
     (so the pin above is not vacuous)."""
