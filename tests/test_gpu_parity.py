@@ -156,6 +156,45 @@ def test_constant_volume_geometric_series():
     g.close()
 
 
+def _fresnel_unpolarised(n1, n2, cos_i):
+    """Transmittance (mean of s and p) and cos of the refracted angle."""
+    cos_t = math.sqrt(1.0 - (n1 / n2) ** 2 * (1.0 - cos_i * cos_i))
+    rs = (n1 * cos_i - n2 * cos_t) / (n1 * cos_i + n2 * cos_t)
+    rp = (n2 * cos_i - n1 * cos_t) / (n2 * cos_i + n1 * cos_t)
+    return 1.0 - 0.5 * (rs * rs + rp * rp), cos_t
+
+
+def test_central_column_closed_form():
+    # closed form, no oracle: thin lens, refracting vial, chief rays, V = 1.
+    # The chief ray of the centre column (odd grid) lies in the plane through
+    # the vial axis, so it stays there through both walls; its incidence
+    # angles are its tilt and the refracted tilt, and its resin chord is
+    # 2 R_i / cos(tilt in the resin).  The pixel collects T1 T2 times the
+    # attenuated geometric series of that chord, at every angle.
+    n = 49
+    F = (n / 2) / math.tan(math.radians(10))
+    p = dict(nx=n, ny=n, nz=n, nu=n, nv=n, pitch_u=1.0, pitch_v=1.0, n_angles=3,
+             angles=np.array([0.0, 2.3, 4.0]), projector=1, focus=F, pupil=F * math.tan(math.radians(6.1)),
+             n_pupil=1, pupil_xy=np.zeros((1, 2)), flags=0, r_outer=0.47 * n, r_inner=0.44 * n, n_air=1.0,
+             n_glass=1.47, n_resin=1.49, alpha=0.02, step=0.5)
+    want = []
+    for v in range(n):
+        z = v - (n - 1) / 2
+        T1, c1 = _fresnel_unpolarised(p["n_air"], p["n_glass"], F / math.hypot(F, z))
+        T2, c2 = _fresnel_unpolarised(p["n_glass"], p["n_resin"], c1)
+        K = math.floor(2.0 * p["r_inner"] / c2 / p["step"] + 0.5)
+        q = math.exp(-p["alpha"] * p["step"])
+        want.append(T1 * T2 * p["step"] * math.exp(-p["alpha"] * p["step"] / 2) * (1.0 - q ** K) / (1.0 - q))
+    want = np.array(want)
+    g = gpu_geom(p)
+    P = g.forward(to_dev(np.ones((n, n, n)))).double().cpu().numpy()
+    rows = slice(5, n - 5)   # the ray's z drift keeps its stencil inside the grid
+    err = np.abs(P[:, rows, n // 2] - want[None, rows]).max() / want.max()
+    say("central column: max error %.2e of the largest pixel (%.4f)" % (err, want.max()))
+    assert err <= 2e-6
+    g.close()
+
+
 def test_c1_full_forward_and_adjoint():
     p = synth.workload("c1")
     t, _ = synth.random_config1_target(64, 32.0, seed=0)
