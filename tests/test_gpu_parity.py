@@ -584,6 +584,30 @@ def test_c2_full_adjoint_one_angle(c2_full):
     g.set_adjoint_variant(vam.ADJ_DEFAULT)
 
 
+def test_c2_full_quarter_turn_symmetry(c2_full):
+    # a property that holds at any size, here the benchmark's full workload:
+    # the vial turns about z, so turning the volume by 90 degrees is the same
+    # as projecting 90 angles (90 degrees) later, and the deposit of angles
+    # [90, 180) turned back equals the deposit of the same projections at
+    # angles [0, 90)
+    p, t, g = c2_full
+    n = p["nx"]
+    rng = synth.SplitMix64(29)
+    V = to_dev(rng.uniform(n ** 3).reshape(n, n, n))
+    rot = lambda a: a.transpose(1, 2).flip(2).contiguous()   # V'[z, j, i] = V[z, n-1-i, j]
+    say("c2 full quarter-turn symmetry")
+    P = g.forward(V)
+    Pr = g.forward(rot(V))
+    ef = float((P[90:].double() - Pr[:270].double()).norm() / P[90:].double().norm())
+    y = torch.from_numpy(rng.uniform(90 * 256 * 256).reshape(90, 256, 256).astype(np.float32)).to(DEV)
+    D90 = g.back(y, angle_begin=90).double()
+    D0 = g.back(y, angle_begin=0).double()
+    ed = float((rot(D90) - D0).norm() / D0.norm())
+    say("forward: P[a + 90](V) vs P[a](rot V) rel-L2 %.3e; deposit: rot(D[90, 180)) vs D[0, 90) rel-L2 %.3e"
+        % (ef, ed))
+    assert ef <= 1e-6 and ed <= 1e-6
+
+
 def test_c2_full_adjoint_identity(c2_full):
     p, t, g = c2_full
     rng = synth.SplitMix64(23)
