@@ -115,7 +115,8 @@ vam_status vam_destroy_geometry(vam_geometry_t h);
  * angle_begin+angle_count-1 from vol[nz][ny][nx].  vol_t and proj_t select
  * the element types.  Deterministic: the same inputs give the same bits.
  * Errors: VAM_ERR_BAD_HANDLE; VAM_ERR_INVALID_ARG for NULL pointers, bad
- * dtypes or an angle range outside [0, n_angles); VAM_ERR_HIP. */
+ * dtypes, angle_count < 1 or an angle range outside [0, n_angles);
+ * VAM_ERR_HIP. */
 vam_status vam_forward_project(vam_geometry_t h, const void* vol, vam_dtype vol_t,
                                void* proj, vam_dtype proj_t,
                                int32_t angle_begin, int32_t angle_count,

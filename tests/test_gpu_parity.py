@@ -302,9 +302,13 @@ def test_angle_ranges_determinism_accumulate():
     d_a = g.back(y[:4], angle_begin=0)
     g.back(y[4:], out=d_a, accumulate=True, angle_begin=4)
     assert relL2(d_a.double().cpu().numpy(), d_all.cpu().numpy()) <= 1e-6
-    # out-of-range angle windows are rejected
+    # out-of-range and empty angle windows are rejected
     with pytest.raises(vam.VamError):
         g.forward(x, angle_begin=8, angle_count=5)
+    with pytest.raises(vam.VamError):
+        g.forward(x, angle_begin=2, angle_count=0)
+    with pytest.raises(vam.VamError):
+        g.back(y[:0], angle_begin=2)
     with pytest.raises(vam.VamError):
         g.back(y[:3], angle_begin=9)
     g.close()
