@@ -50,9 +50,10 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def load_traffic(kernel):
-    """HBM bytes per launch from committed rocprofv3 counter runs, or None
-    when the kernel source changed since they were taken."""
+def load_counters(kernel):
+    """The committed rocprofv3 counter record of a kernel per launch (HBM
+    fetch / write bytes, VALU wave-instructions, L1->L2 bytes), or None when
+    the kernel sources changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", "traffic_c2.json")
     if not os.path.exists(path):
         return None
@@ -62,8 +63,36 @@ def load_traffic(kernel):
         return None
     if d.get("source_sha256") != kernel_source_hash() or kernel not in d:
         return None
-    k = d[kernel]
+    return d[kernel]
+
+
+def load_traffic(kernel):
+    """HBM bytes per launch from committed rocprofv3 counter runs, or None
+    when the kernel source changed since they were taken."""
+    k = load_counters(kernel)
+    if k is None:
+        return None
     return k.get("fetch_bytes", 0) + k.get("write_bytes", 0)
+
+
+def counter_rates(kernel, launch_ms):
+    """HBM and L2 bandwidth and VALU issue use of a kernel: its committed
+    per-launch counter totals over this run's launch time.  VALU issue busy
+    = wave-instructions x 2 cycles / (1024 SIMDs x 2.4 GHz x time), the
+    rate at which MI355X issues one wave64 VALU instruction per SIMD every
+    two cycles."""
+    k = load_counters(kernel)
+    if k is None or not launch_ms:
+        return None
+    sec = launch_ms * 1e-3
+    hbm = (k.get("fetch_bytes", 0) + k.get("write_bytes", 0)) / sec / 1e9
+    out = {"kernel": kernel, "source": "profiles/traffic_c2.json",
+           "hbm_GBps": hbm, "hbm_frac": hbm / PEAK_HBM_GBPS}
+    if "l2_read_bytes" in k:
+        out["l2_read_TBps"] = k["l2_read_bytes"] / sec / 1e12
+    if "valu_insts" in k:
+        out["valu_issue_busy"] = k["valu_insts"] * 2.0 / (1024 * 2.4e9 * sec)
+    return out
 
 
 def learned_vs_plain():
@@ -249,7 +278,8 @@ def main():
     dom, dom_ms = ("deposit", b_avg) if b_avg >= f_avg else ("forward", f_avg)
     flop = FLOP_PER_SAMPLE * samples_per_pass
     achieved = flop / (dom_ms * 1e-3) / 1e12
-    traffic = load_traffic(dom) if (args.workload, args.dtype) == ("c2", "f32") else None
+    profiled = (args.workload, args.dtype) == ("c2", "f32")
+    traffic = load_traffic(dom) if profiled else None
     roofline = {
         "bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
         "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": traffic,
@@ -270,6 +300,7 @@ def main():
                        "sparse_nonzero_pixel_fraction": active},
         "gather_model": {"bytes_per_sample": GATHER_BYTES_PER_SAMPLE, "kernel": dom,
                          "GBps": gather_gbps, "frac_of_hbm_peak": gather_gbps / PEAK_HBM_GBPS},
+        "counters": counter_rates(dom, dom_ms) if profiled else None,
         "setup_s": t_setup, "wall_s": wall,
         "learned_vs_plain": learned_vs_plain(),
     }

@@ -2,7 +2,7 @@
 
     python -m paper_2211_03516_amd.profiling stats <run_kernel_stats.csv> [--cmd "..."]
     python -m paper_2211_03516_amd.profiling counters <run_counter_collection.csv> [--cmd "..."]
-    python -m paper_2211_03516_amd.profiling traffic <fetch.csv> <write.csv> --copy-mib N [--out f.json]
+    python -m paper_2211_03516_amd.profiling traffic <fetch.csv> <write.csv> --copy-mib N [--sq sq.csv] [--l2 l2.csv] [--out f.json]
     python -m paper_2211_03516_amd.profiling l2 <l2 counters.csv> <run_kernel_stats.csv> --copy-mib N --calls ...
 
 `stats` prints the per-kernel table (calls, average / total milliseconds,
@@ -55,12 +55,34 @@ def kernel_source_hash(root):
     return h.hexdigest()
 
 
-def traffic(fetch_csv, write_csv, copy_mib, root, calls=None):
+def _sums(path, counters):
+    """{kernel: {counter: (sum over dispatches, dispatches)}} for the main
+    kernels, and {counter: largest value of a copy kernel dispatch}."""
+    per = collections.defaultdict(lambda: collections.defaultdict(lambda: [0.0, 0]))
+    copy = collections.defaultdict(float)
+    for r in csv.DictReader(open(path)):
+        c, v = r["Counter_Name"], float(r["Counter_Value"])
+        if c not in counters:
+            continue
+        if "copyBuffer" in r["Kernel_Name"]:
+            copy[c] = max(copy[c], v)
+        for name, pat in KERNELS.items():
+            if pat in r["Kernel_Name"]:
+                per[name][c][0] += v
+                per[name][c][1] += 1
+    return per, copy
+
+
+def traffic(fetch_csv, write_csv, copy_mib, root, calls=None, sq_csv=None, l2_csv=None):
     """HBM bytes per call of the main kernels (a call = one operator pass,
     which may be several dispatches), with FETCH_SIZE and WRITE_SIZE each
     scaled by what they read for the largest copy kernel (a device copy of
     copy_mib MiB: reads and writes exactly that much).  `calls` maps each
-    kernel to the number of operator passes in the profiled run."""
+    kernel to the number of operator passes in the profiled run.  With
+    sq_csv, also the VALU wave-instructions per call (SQ_INSTS_VALU); with
+    l2_csv (a run with the same copy), the L1 -> L2 read and write bytes per
+    call (TCP_TCC_READ_REQ_sum / TCP_TCC_WRITE_REQ_sum times the copy's
+    bytes per request)."""
     calls = calls or {}
     def load(path, counter):
         rows = [r for r in csv.DictReader(open(path)) if r["Counter_Name"] == counter]
@@ -85,6 +107,21 @@ def traffic(fetch_csv, write_csv, copy_mib, root, calls=None):
             f = sum(fetch[name]) / c * ff * 1024
             w = sum(write[name]) / c * fw * 1024
             out[name] = {"fetch_bytes": f, "write_bytes": w, "dispatches_per_call": len(fetch[name]) / c}
+    if sq_csv:
+        per, _ = _sums(sq_csv, {"SQ_INSTS_VALU"})
+        for name in KERNELS:
+            if name in out and "SQ_INSTS_VALU" in per[name]:
+                out[name]["valu_insts"] = per[name]["SQ_INSTS_VALU"][0] / calls.get(name, 1)
+    if l2_csv:
+        per, copy = _sums(l2_csv, {"TCP_TCC_READ_REQ_sum", "TCP_TCC_WRITE_REQ_sum"})
+        nbytes = copy_mib * 1048576.0
+        rd = nbytes / copy["TCP_TCC_READ_REQ_sum"] if copy.get("TCP_TCC_READ_REQ_sum") else None
+        wr = nbytes / copy["TCP_TCC_WRITE_REQ_sum"] if copy.get("TCP_TCC_WRITE_REQ_sum") else None
+        for name in KERNELS:
+            if name in out and rd and wr and "TCP_TCC_READ_REQ_sum" in per[name]:
+                c = calls.get(name, 1)
+                out[name]["l2_read_bytes"] = per[name]["TCP_TCC_READ_REQ_sum"][0] * rd / c
+                out[name]["l2_write_bytes"] = per[name]["TCP_TCC_WRITE_REQ_sum"][0] * wr / c
     return out
 
 
@@ -146,11 +183,13 @@ def main(argv=None):
     ap.add_argument("--copy-mib", type=float, default=1024.0)
     ap.add_argument("--calls", default="", help="operator passes per kernel in the run, e.g. forward=2,deposit=1")
     ap.add_argument("--out", default=None)
+    ap.add_argument("--sq", default=None, help="traffic: also SQ_INSTS_VALU from this counter CSV")
+    ap.add_argument("--l2", default=None, help="traffic: also L1->L2 bytes from this counter CSV")
     a = ap.parse_args(argv)
     if a.what == "traffic":
         root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
         calls = {k: int(v) for k, v in (kv.split("=") for kv in a.calls.split(",") if kv)}
-        d = traffic(a.path, a.path2, a.copy_mib, root, calls)
+        d = traffic(a.path, a.path2, a.copy_mib, root, calls, sq_csv=a.sq, l2_csv=a.l2)
         if a.cmd:
             d["command"] = a.cmd
         text = json.dumps(d, indent=1)

@@ -38,3 +38,14 @@ def test_traffic_only_for_the_profiled_sources(monkeypatch):
         assert got == t["deposit"]["fetch_bytes"] + t["deposit"]["write_bytes"]
     monkeypatch.setattr(bench, "kernel_source_hash", lambda: "0" * 64)
     assert bench.load_traffic("deposit") is None
+
+
+def test_counter_rates_follow_the_launch_time(monkeypatch):
+    rec = {"fetch_bytes": 3e9, "write_bytes": 1e9, "valu_insts": 1024 * 2.4e9 / 2, "l2_read_bytes": 2e12}
+    monkeypatch.setattr(bench, "load_counters", lambda kernel: rec)
+    r = bench.counter_rates("deposit", 1000.0)     # one second
+    assert r["hbm_GBps"] == 4.0 and r["hbm_frac"] == 4.0 / 8000.0
+    assert r["l2_read_TBps"] == 2.0
+    assert abs(r["valu_issue_busy"] - 1.0) < 1e-12   # one wave64 instruction per SIMD every 2 cycles
+    monkeypatch.setattr(bench, "load_counters", lambda kernel: None)
+    assert bench.counter_rates("deposit", 1000.0) is None

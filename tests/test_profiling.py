@@ -65,3 +65,16 @@ def test_committed_traffic_file_is_well_formed():
         assert d[k]["fetch_bytes"] > 0 and d[k]["write_bytes"] > 0
     assert 1.9 < d["fetch_scale"] < 2.1 and 0.9 < d["write_scale"] < 1.1
     assert "rocprofv3 --pmc FETCH_SIZE" in d["command"] and "rocprofv3 --pmc WRITE_SIZE" in d["command"]
+
+
+def test_traffic_with_valu_and_l2_counters(tmp_path):
+    f, w, q, l = (tmp_path / n for n in ("f.csv", "w.csv", "sq.csv", "l2.csv"))
+    _counters(f, [(COPY, "FETCH_SIZE", 512), (DEP, "FETCH_SIZE", 100)])
+    _counters(w, [(COPY, "WRITE_SIZE", 1024), (DEP, "WRITE_SIZE", 10)])
+    _counters(q, [(DEP, "SQ_INSTS_VALU", 7e9), (DEP, "SQ_LDS_BANK_CONFLICT", 5.0)])
+    # a 1 MiB copy: 8192 read requests (128 B each), 16384 write requests (64 B)
+    _counters(l, [(COPY, "TCP_TCC_READ_REQ_sum", 8192), (COPY, "TCP_TCC_WRITE_REQ_sum", 16384),
+                  (DEP, "TCP_TCC_READ_REQ_sum", 1000), (DEP, "TCP_TCC_WRITE_REQ_sum", 10)])
+    d = profiling.traffic(str(f), str(w), 1.0, ROOT, {"deposit": 1}, sq_csv=str(q), l2_csv=str(l))
+    assert d["deposit"]["valu_insts"] == 7e9
+    assert d["deposit"]["l2_read_bytes"] == 128000.0 and d["deposit"]["l2_write_bytes"] == 640.0
