@@ -612,6 +612,33 @@ def test_c2_full_quarter_turn_symmetry(c2_full):
     assert ef <= 1e-6 and ed <= 1e-6
 
 
+def test_c2_full_mirror_symmetry(c2_full):
+    # a property that holds at any size: mirroring the optics in x (pupil
+    # points x -> -x) and the volume in x is the same as flipping every
+    # projection in u with the angles reversed (theta -> -theta); the
+    # deposit follows as the transpose
+    p, t, g = c2_full
+    na = p["n_angles"]
+    pm = dict(p)
+    pm["pupil_xy"] = np.asarray(p["pupil_xy"]) * np.array([-1.0, 1.0])
+    gm = gpu_geom(pm)
+    perm = torch.tensor([(na - a) % na for a in range(na)], device=DEV)
+    rng = synth.SplitMix64(31)
+    V = to_dev(t * rng.uniform(t.size).reshape(t.shape))
+    P = g.forward(V).double()
+    Pm = gm.forward(V.flip(2).contiguous()).double()
+    ef = float((P - Pm[perm].flip(2)).norm() / P.norm())
+    y = torch.from_numpy(rng.uniform(na * 256 * 256).reshape(na, 256, 256).astype(np.float32)).to(DEV)
+    ym = torch.empty_like(y)
+    ym[perm] = y.flip(2)
+    D = g.back(y).double()
+    Dm = gm.back(ym.contiguous()).double()
+    ed = float((D - Dm.flip(2)).norm() / D.norm())
+    say("mirror: forward rel-L2 %.3e, deposit rel-L2 %.3e" % (ef, ed))
+    assert ef <= 1e-6 and ed <= 1e-6
+    gm.close()
+
+
 def test_c2_full_adjoint_identity(c2_full):
     p, t, g = c2_full
     rng = synth.SplitMix64(23)
