@@ -1227,10 +1227,18 @@ static vam_status forward_box_t(vam_geometry* h, const MarchParams& P0, PT* proj
   if (!h->seg_part) {
     // partial sums for a chunk of angles, at most ~8 GiB (5 chunks of 80
     // angles at 256^3 with 16 pupil samples: 1.7 % faster than 2 GiB chunks,
-    // fewer launch tails and reductions)
-    h->seg_part_angles = (int)std::max<int64_t>(1, std::min<int64_t>(D.n_angles, (int64_t(1) << 31) / per_angle));
-    VAM_HIP_TRY(hipMalloc(&h->seg_part, per_angle * h->seg_part_angles * sizeof(float)),
-                "allocating segment partial sums");
+    // fewer launch tails and reductions); if the device cannot hold that
+    // much, halve the chunk until the allocation succeeds
+    int64_t angles = std::max<int64_t>(1, std::min<int64_t>(D.n_angles, (int64_t(1) << 31) / per_angle));
+    for (;;) {
+      const hipError_t e = hipMalloc(&h->seg_part, per_angle * angles * sizeof(float));
+      if (e == hipSuccess) break;
+      h->seg_part = nullptr;
+      if (e != hipErrorOutOfMemory || angles == 1) return hip_check(e, "allocating segment partial sums");
+      (void)hipGetLastError();  // the failed allocation's error is handled here
+      angles = (angles + 1) / 2;
+    }
+    h->seg_part_angles = (int)angles;
   }
   const BoxParams Bp = box_params(h);
   const size_t lds = (size_t)h->box_cells * sizeof(float);
