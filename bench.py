@@ -133,10 +133,26 @@ def cpu_baseline(p, target, threads):
     dt = time.perf_counter() - t0
     for a in angles:
         n_samples += 2 * oracle.count_samples(og, a0=a, na=1, nthreads=threads)
+    # the same oracle on one host thread: the forward of one angle
+    n1 = oracle.count_samples(og, a0=angles[0], na=1, nthreads=threads)
+    t1 = time.perf_counter()
+    oracle.forward(og, target, a0=angles[0], na=1, nthreads=1)
+    dt1 = time.perf_counter() - t1
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     return {
         "value": n_samples / dt, "unit": "samples/s", "cores": threads, "kind": "oracle",
         "sample": "forward + dose deposit of angles %d and %d of the same workload " % tuple(angles) +
                   "(%d samples, %.1f s wall, FP64 C++ std::thread)" % (n_samples, dt),
+        "single_thread": {"value": n1 / dt1, "unit": "samples/s",
+                          "sample": "forward of angle %d on one thread (%d samples, %.1f s)" % (angles[0], n1, dt1)},
+        "host": {"cpu_model": model, "logical_cpus": os.cpu_count()},
     }
 
 
