@@ -105,3 +105,27 @@ def continuum_ray_integral(p, vol, e, d, L, w, theta, sub=64):
         tent = np.prod(np.maximum(0.0, 1.0 - diff), axis=2)
         total += float(np.sum(np.exp(-p["alpha"] * sb) * (tent @ V))) * h
     return w * total
+
+
+def count_samples(p, rays, angles):
+    """Samples (over the given angles, radians) whose anti-aliasing stencil
+    touches the grid, counted by brute force: a sample counts when its tent
+    weight prod(max(0, 1 - |p - c|)) is nonzero for at least one voxel
+    centre c of the grid, every centre tried.  (The operator's stencil
+    takes the 8 centres around the sample; it touches the grid exactly when
+    one of them carries weight, apart from samples lying exactly on a cell
+    face one voxel outside the grid, which have probability zero here.)"""
+    C = voxel_centres(p)
+    ds = p["step"]
+    total = 0
+    for th in angles:
+        ct, st = math.cos(th), math.sin(th)
+        for (_u, _v, e, d, L, _w) in rays:
+            K = int(math.floor(L / ds + 0.5))
+            s = (np.arange(K) + 0.5) * ds
+            q = e[None, :] + s[:, None] * d[None, :]
+            pv = np.stack([ct * q[:, 0] + st * q[:, 1], -st * q[:, 0] + ct * q[:, 1],
+                           q[:, 2]], axis=1)
+            tent = np.prod(np.maximum(0.0, 1.0 - np.abs(pv[:, None, :] - C[None, :, :])), axis=2)
+            total += int(np.count_nonzero(tent.max(axis=1) > 0.0))
+    return total

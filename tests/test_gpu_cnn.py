@@ -1,6 +1,7 @@
 """GPU tests of the learned-initialiser network (include/vam_cnn.h): MFMA
-forward, loss and gradients against the CPU reference with the same BF16
-rounding points, determinism, the Adam update, and learning a fixed filter."""
+forward, loss and gradients against the plain FP64 CPU network, within a
+bound that the reference's BF16 error model sets before the GPU runs;
+determinism, the Adam update, and learning a fixed filter."""
 import sys
 
 import numpy as np
@@ -35,41 +36,49 @@ def _setup(L, C, H, W, n, seed, s0=0.05, s1=2.0):
     return p, x, t, (s0, s1)
 
 
+# Bound on the GPU's deviation from the plain FP64 network: LAMBDA times the
+# root-mean-square error that the BF16 error model of oracle.cnn predicts
+# for this network and input (independent relative errors, uniform on
+# [-2^-8, 2^-8], at every value the library stores in BF16).  An error that
+# is a sum of many such independent terms exceeds three times its RMS with
+# small probability; the model is computed on the CPU from the FP64
+# network alone.
+LAMBDA = 3.0
+
+
 @pytest.mark.parametrize("L,C,H,W,n", [(6, 64, 24, 40, 3), (3, 16, 17, 15, 32), (2, 8, 8, 4, 1)])
 def test_cnn_matches_oracle(L, C, H, W, n):
     p, x, t, (s0, s1) = _setup(L, C, H, W, n, seed=L * 100 + C)
-    say("cnn L %d C %d %dx%d n %d" % (L, C, H, W, n))
+    p64 = p.astype(np.float64)
+    xf, tf = x.astype(np.float32).astype(np.float64), t.astype(np.float32).astype(np.float64)
+    model = ocnn.rounding_model(p64, xf, tf, L, C, s0, s1, draws=8, seed=L * 100 + C)
+    say("cnn L %d C %d %dx%d n %d; BF16 error model: out %.2e loss %.2e grads %s"
+        % (L, C, H, W, n, model["out"], model["loss"], np.array2string(model["grads"], precision=2)))
     net = vam.Cnn(L, C, H, W, max_batch=n, in_scale=(s0, s1))
     net.set_params(p)
     assert np.array_equal(net.get_params(), p)
-    p64 = p.astype(np.float64)
     xd = torch.from_numpy(x).float().to(DEV)
     td = torch.from_numpy(t).float().to(DEV)
-    xf, tf = x.astype(np.float32).astype(np.float64), t.astype(np.float32).astype(np.float64)
     y = net.forward(xd).cpu().numpy()
-    y_ref, _ = ocnn.forward(p64, xf, L, C, s0, s1, bf16=True)
-    # compare the network's own contribution z / s1 = y - x1
-    e_y = relL2(y - xf[:, 1], y_ref - xf[:, 1])
     loss = net.loss_grad(xd, td)
     g = net.grads().astype(np.float64)
-    loss_ref, g_ref = ocnn.loss_grad(p64, xf, tf, L, C, s0, s1, bf16=True)
+    # the plain FP64 network; compare the network's own contribution
+    # z / s1 = y - x1
+    y_ref, _ = ocnn.forward(p64, xf, L, C, s0, s1)
+    loss_ref, g_ref = ocnn.loss_grad(p64, xf, tf, L, C, s0, s1)
+    e_y = relL2(y - xf[:, 1], y_ref - xf[:, 1])
     e_l = abs(loss - loss_ref) / loss_ref
-    e_g = relL2(g, g_ref)
-    # per layer
-    off, worst = 0, 0.0
-    for ci, co in ocnn.layer_shapes(L, C):
-        k = co * 9 * ci + co
-        worst = max(worst, relL2(g[off:off + k], g_ref[off:off + k]))
-        off += k
-    _, g_exact = ocnn.loss_grad(p64, xf, tf, L, C, s0, s1, bf16=False)
-    say("  forward %.2e  loss %.2e  grads %.2e (worst layer %.2e); BF16 storage vs FP64: grads %.2e"
-        % (e_y, e_l, e_g, worst, relL2(g, g_exact)))
-    # Bound: both sides round to BF16 at the same points, but FP32 (GPU) and
-    # FP64 (reference) sums differ by ~1e-6 relative, which moves a fraction
-    # ~2e-6 / 2^-7 ~ 3e-4 of the stored values across a BF16 rounding
-    # boundary; each such flip is one BF16 ulp (2^-7 relative), ~1.5e-4
-    # rel-L2 per layer, compounding over up to six layers.
-    assert e_y <= 3e-3 and e_l <= 1e-4 and worst <= 3e-3
+    e_g = np.array([relL2(g[s], g_ref[s]) for s in ocnn.layer_slices(L, C)])
+    # diagnostic only: the same network with BF16 rounding emulated at the
+    # storage points
+    y_em, _ = ocnn.forward(p64, xf, L, C, s0, s1, bf16=True)
+    _, g_em = ocnn.loss_grad(p64, xf, tf, L, C, s0, s1, bf16=True)
+    say("  vs FP64: out %.2e loss %.2e grads %s; vs BF16 emulation: out %.2e grads %.2e"
+        % (e_y, e_l, np.array2string(e_g, precision=2), relL2(y - xf[:, 1], y_em - xf[:, 1]),
+           relL2(g, g_em)))
+    assert e_y <= LAMBDA * model["out"]
+    assert e_l <= LAMBDA * model["loss"]
+    assert np.all(e_g <= LAMBDA * model["grads"])
     net.close()
 
 

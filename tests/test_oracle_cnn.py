@@ -78,3 +78,27 @@ def test_backward_matches_central_differences(bf16):
     fd = np.array(fd)
     assert np.abs(grad[idx] - fd).max() <= 1e-7 * max(1.0, np.abs(fd).max())
     assert np.abs(fd).max() > 1e-3       # the sampled parameters matter
+
+
+def test_rounding_model_matches_its_closed_form_on_one_layer():
+    # One convolution from two input channels, z = conv(a, w) + b, with the
+    # inputs a and the weights w stored.  To first order in u,
+    # dz_p = sum_{c,k} w_ck a_{c,p+k} (d_w,ck + d_a,c,p+k), and every d in
+    # that sum is a different independent U[-u, u] variable (variance
+    # u^2 / 3), so E|dz|^2 = 2 (u^2 / 3) sum_p sum_{c,k} (w_ck a_{c,p+k})^2,
+    # i.e. conv(a^2, w^2) summed.  The model's RMS over many draws must
+    # reproduce it; perturbing only one of the two stores, or a variance
+    # other than u^2 / 3, would miss it by a factor of sqrt(2) or more.
+    L, C, s0, s1 = 1, 4, 0.8, 1.7
+    rng = synth.SplitMix64(105)
+    params = rng.uniform(synth.cnninit.param_count(L, C)) - 0.5
+    x = rng.uniform(3 * 2 * 9 * 11).reshape(3, 2, 9, 11)
+    t = rng.uniform(3 * 9 * 11).reshape(3, 9, 11)
+    (w, b), = cnn.unpack(params, L, C)
+    xt = torch.from_numpy(x)
+    a = torch.stack([s0 * xt[:, 0], s1 * xt[:, 1]], dim=1)
+    z = F.conv2d(a, w, b, padding=1)
+    e2 = 2.0 * cnn.U_BF16 ** 2 / 3.0 * float(F.conv2d(a * a, w * w, padding=1).sum())
+    want = np.sqrt(e2) / float(z.norm())
+    got = cnn.rounding_model(params, x, t, L, C, s0, s1, draws=400, seed=3)["out"]
+    assert abs(got / want - 1.0) < 0.05, (got, want)

@@ -530,3 +530,31 @@ def test_count_samples_matches_trace():
     # every c1 sample lies inside the grid's stencil range, so the count is
     # sum of K over rays times the angles
     assert oracle.count_samples(g) == 3 * int(R[..., 21].sum())
+
+
+@pytest.mark.parametrize("kind", ["straight", "refracting"])
+def test_count_samples_brute_force_rays_leaving_the_grid(kind):
+    """The sample count (the throughput metric's denominator) where rays
+    leave the grid: the resin is wider than the grid in x and y, and tilted
+    rays leave through the top and bottom, so some samples have no voxel
+    in reach and others reach it with only part of their stencil.  Counted
+    by brute force against every voxel centre."""
+    if kind == "straight":
+        p = _geom(nx=9, ny=8, nz=7, nu=14, nv=10, n_pupil=3, pupil=0.35,
+                  r_outer=6.5, r_inner=6.5, step=0.5, n_angles=3,
+                  pitch_u=0.95, pitch_v=1.05, angles=np.array([0.0, 0.61, 2.2]))
+        rays = brute.straight_rays(p)
+    else:
+        p = _c2_small(10, 3, nu=16, nv=14, nz=8, r_outer=7.4, r_inner=6.9, step=0.45,
+                      n_angles=3, angles=np.array([0.3, 1.9, 4.4]))
+        rays = brute.rays_from_records(p, oracle.trace(oracle.Geometry(p)))
+    g = oracle.Geometry(p)
+    n_all = sum(int(math.floor(r[4] / p["step"] + 0.5)) for r in rays) * len(p["angles"])
+    want = brute.count_samples(p, rays, p["angles"])
+    got = oracle.count_samples(g)
+    # the case is one that exercises the rule: many samples fall outside
+    assert 0 < want < 0.8 * n_all, (want, n_all)
+    assert got == want
+    # and per angle
+    for a in range(len(p["angles"])):
+        assert oracle.count_samples(g, a, 1) == brute.count_samples(p, rays, p["angles"][a:a + 1])
