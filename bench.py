@@ -20,10 +20,17 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Algorithmic arithmetic of one ray-voxel sample (both operators): position
-# 3 FMA (6), fractional offsets 3, trilinear weights or lerps 21, attenuation
-# argument and exp2 2, scaling and accumulation 2 = 34 FLOP.
-FLOP_PER_SAMPLE = 34
+# Algorithmic arithmetic of one ray-voxel sample, counting an FMA as 2 FLOP
+# (the convention of the 157.3 TFLOP/s FP32 vector peak):
+#   forward: position 3 FMA (6), fractional offsets 3, seven lerps of one
+#            subtraction and one FMA (21), attenuated accumulation S r + v
+#            (one FMA, 2) = 32;
+#   deposit: position 3 FMA (6), fractional offsets 3, the z and y weight
+#            splits (6), the x split of four weights (8), the eight corner
+#            sums (8), the attenuation e r (1) = 32.
+# (The same work counted in lane operations, an FMA once, is ~25-30 per
+# sample.)
+FLOP_PER_SAMPLE = {"forward": 32, "deposit": 32}
 # Gather-byte model: the 8 FP32 corner values a sample reads (or updates).
 GATHER_BYTES_PER_SAMPLE = 32
 PEAK_FP32_VECTOR_TFLOPS = 157.3
@@ -75,23 +82,27 @@ def load_traffic(kernel):
     return k.get("fetch_bytes", 0) + k.get("write_bytes", 0)
 
 
-def counter_rates(kernel, launch_ms):
-    """HBM and L2 bandwidth and VALU issue use of a kernel: its committed
-    per-launch counter totals over this run's launch time.  VALU issue busy
-    = wave-instructions x 2 cycles / (1024 SIMDs x 2.4 GHz x time), the
-    rate at which MI355X issues one wave64 VALU instruction per SIMD every
-    two cycles."""
+def counter_rates(kernel, launch_ms, samples):
+    """HBM and L2 bandwidth and VALU use of a kernel: the committed rocprofv3
+    counter totals per launch (taken on the same kernel sources, not in this
+    run) over this run's launch time.  VALU issue busy = wave-instructions x
+    2 cycles / (1024 SIMDs x 2.4 GHz x time), the rate at which MI355X issues
+    one wave64 VALU instruction per SIMD every two cycles; VALU lane slots
+    per sample = wave-instructions x 64 / samples."""
     k = load_counters(kernel)
     if k is None or not launch_ms:
         return None
     sec = launch_ms * 1e-3
     hbm = (k.get("fetch_bytes", 0) + k.get("write_bytes", 0)) / sec / 1e9
-    out = {"kernel": kernel, "source": "profiles/traffic_c2.json",
+    out = {"kernel": kernel, "source": "committed rocprofv3 counters, profiles/traffic_c2.json",
            "hbm_GBps": hbm, "hbm_frac": hbm / PEAK_HBM_GBPS}
     if "l2_read_bytes" in k:
         out["l2_read_TBps"] = k["l2_read_bytes"] / sec / 1e12
     if "valu_insts" in k:
         out["valu_issue_busy"] = k["valu_insts"] * 2.0 / (1024 * 2.4e9 * sec)
+        out["valu_lane_slots_per_sample"] = k["valu_insts"] * 64.0 / samples
+    if "valu_thread_cycles" in k:
+        out["valu_active_lane_cycles_per_sample"] = k["valu_thread_cycles"] / samples
     return out
 
 
@@ -167,14 +178,11 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--adjoint-variant", type=int, default=0)
     ap.add_argument("--forward-variant", type=int, default=0)
-    ap.add_argument("--box-edge", type=int, default=0)
-    ap.add_argument("--fixed", type=int, default=1)
+    ap.add_argument("--box-edge", type=int, default=0, help="lab box edge: 8, 12 or 16")
     ap.add_argument("--seg-order", type=int, default=-1, help="segment order of the deposit")
     ap.add_argument("--seg-order-fwd", type=int, default=-1, help="segment order of the forward")
     ap.add_argument("--deposit-threads", type=int, default=0)
-    ap.add_argument("--work-order", type=int, default=-1, help="bit 0 forward, bit 1 deposit: XCD-aware")
     ap.add_argument("--angle-block", default="", help="deposit[,forward] angle blocks of the XCD-aware work order")
-    ap.add_argument("--forward-cache", type=int, default=-1, help="1/0: forward keeps the current cell in registers")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
@@ -212,17 +220,12 @@ def main():
     g.set_forward_variant(args.forward_variant)
     if args.box_edge:
         g.set_box_edge(args.box_edge)
-    g.set_fixed_kernels(args.fixed)
     if args.seg_order >= 0:
         g.set_segment_order(args.seg_order)
     if args.seg_order_fwd >= 0:
         g.set_segment_order(args.seg_order_fwd, forward=True)
     if args.deposit_threads:
         g.set_deposit_threads(args.deposit_threads)
-    if args.work_order >= 0:
-        g.set_work_order(args.work_order & 1, args.work_order >> 1)
-    if args.forward_cache >= 0:
-        g.set_forward_cache(args.forward_cache)
     if args.angle_block:
         ab = [int(v) for v in args.angle_block.split(",")]
         g.set_angle_blocks(deposit=ab[0], forward=ab[1] if len(ab) > 1 else None)
@@ -292,14 +295,15 @@ def main():
             sparse_ms.append(g.kernel_times()[1])
         active = float((proj != 0).float().mean())
     dom, dom_ms = ("deposit", b_avg) if b_avg >= f_avg else ("forward", f_avg)
-    flop = FLOP_PER_SAMPLE * samples_per_pass
+    flop = FLOP_PER_SAMPLE[dom] * samples_per_pass
     achieved = flop / (dom_ms * 1e-3) / 1e12
     profiled = (args.workload, args.dtype) == ("c2", "f32")
     traffic = load_traffic(dom) if profiled else None
     roofline = {
         "bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
         "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": traffic,
-        "kernel": dom, "flop_per_sample": FLOP_PER_SAMPLE, "launch_ms": dom_ms,
+        "kernel": dom, "flop_per_sample": FLOP_PER_SAMPLE[dom], "flop_convention": "FMA = 2 FLOP",
+        "launch_ms": dom_ms, "samples_per_launch": samples_per_pass,
     }
     gather_gbps = GATHER_BYTES_PER_SAMPLE * samples_per_pass / (dom_ms * 1e-3) / 1e9
     out = {
@@ -316,7 +320,7 @@ def main():
                        "sparse_nonzero_pixel_fraction": active},
         "gather_model": {"bytes_per_sample": GATHER_BYTES_PER_SAMPLE, "kernel": dom,
                          "GBps": gather_gbps, "frac_of_hbm_peak": gather_gbps / PEAK_HBM_GBPS},
-        "counters": counter_rates(dom, dom_ms) if profiled else None,
+        "counters": counter_rates(dom, dom_ms, samples_per_pass) if profiled else None,
         "setup_s": t_setup, "wall_s": wall,
         "learned_vs_plain": learned_vs_plain(),
     }

@@ -132,7 +132,9 @@ vam_status vam_forward_project(vam_geometry_t h, const void* vol, vam_dtype vol_
  * largest cell sum per add), then adds to an FP64 accumulator; the order of
  * those FP64 additions is unspecified (results may differ in the last bits
  * between runs).  A non-finite projection value makes the dose of the lab
- * boxes its rays cross NaN.  Errors as for vam_forward_project. */
+ * boxes its rays cross NaN.  The angle range selects which projections
+ * proj holds (one GPU's share of the angles when the work is split).
+ * Errors as for vam_forward_project. */
 vam_status vam_back_project(vam_geometry_t h, const void* proj, vam_dtype proj_t,
                             float* dose, int32_t accumulate,
                             int32_t angle_begin, int32_t angle_count,
@@ -145,10 +147,17 @@ vam_status vam_back_project(vam_geometry_t h, const void* proj, vam_dtype proj_t
  *   loss = mean over voxels of (sig - target)^2,
  *   grad = A [ (2/N)(sig - target) sig (1-sig) sharpness ],
  *   g <- g - lr grad, then g <- max(g, 0) if clamp_nonneg.
- * target: FP32 [nz][ny][nx]; proj: FP32 [n_angles][n_v][n_u], updated in
- * place; dose (optional, may be NULL): FP32 [nz][ny][nx] receives d; the
- * loss is reduced in FP64.  loss_out (optional) receives the loss of the
- * projections BEFORE the update; passing it synchronises `stream`. */
+ * target: FP32 [nz][ny][nx]; proj: [n_angles][n_v][n_u] of element type
+ * proj_t (FP32, BF16 or FP16), updated in place: the deposit reads the
+ * stored values, the gradient is FP32 and the updated value is rounded to
+ * nearest even on store; dose (optional, may be NULL): FP32 [nz][ny][nx]
+ * receives d; the loss is reduced in FP64.  loss_out (optional) receives the
+ * loss of the projections BEFORE the update; passing it synchronises
+ * `stream`.  The first call allocates the step's buffers (two volumes and
+ * an FP32 gradient of the projections' shape) in the handle.  Errors:
+ * VAM_ERR_BAD_HANDLE; VAM_ERR_INVALID_ARG for NULL pointers, an unknown
+ * dtype or parameters outside the ranges below; VAM_ERR_OUT_OF_MEMORY;
+ * VAM_ERR_HIP. */
 typedef struct {
   double threshold;     /* gelation dose threshold, e.g. 0.8 */
   double sharpness;     /* sigmoid slope kappa, > 0          */
@@ -156,7 +165,7 @@ typedef struct {
   int32_t clamp_nonneg; /* 1: project onto g >= 0            */
 } vam_opt_params;
 
-vam_status vam_optimize_step(vam_geometry_t h, const float* target, float* proj,
+vam_status vam_optimize_step(vam_geometry_t h, const float* target, void* proj, vam_dtype proj_t,
                              float* dose, const vam_opt_params* params,
                              double* loss_out, hipStream_t stream);
 
@@ -204,39 +213,21 @@ vam_status vam_export_rays(vam_geometry_t h, double* out);
 
 /* Select the kernel variant of an operator for this handle (measurement
  * and testing; every variant computes the same operator).
- *   op 0, forward:  0 = default (fastest measured), 1 = plain ray-driven
- *                   kernel, 2 = lab-box tiled (volume staged in LDS),
- *                   3 = tuned ray-driven kernel.
- *   op 1, deposit:  0 = default (fastest measured), 1 = scatter with
- *                   direct FP32 atomics, 2 = scatter with in-register run
- *                   aggregation (FP32 atomics), 3 = as 2 with an FP64
- *                   accumulator, 4 = tuned scatter (FP32 atomics),
- *                   5 = tuned scatter with an FP64 accumulator,
- *                   6 = lab-box tiled with FP64 LDS accumulation,
- *                   7 = lab-box tiled with FP32 LDS accumulation,
- *                   8 = as 6 with in-register run aggregation,
- *                   9 = voxel-driven gather through an inverse ray map
+ *   op 0, forward:  0 = default: lab-box tiled, volume footprint staged in
+ *                   LDS, deterministic per-segment partial sums;
+ *                   1 = ray-driven reference (one lane per pixel and angle,
+ *                   buffer gathers from the padded volume).
+ *   op 1, deposit:  0 = default: lab-box tiled, footprint summed in LDS in
+ *                   32-bit fixed point (the scale of each box and angle
+ *                   bounds every partial sum below 2^31; rounding <= 2^-31
+ *                   of that bound per add; a non-finite projection value
+ *                   makes its footprint NaN), then FP64 global adds;
+ *                   1 = ray-driven reference with FP64 global atomics;
+ *                   2 = voxel-driven gather through an inverse ray map
  *                   (lab-frame unit cells -> sample runs; built on first
- *                   use, ~32 bytes per run; no atomics, fixed order),
- *                   10 = as 8, but consecutive cells share the corners of
- *                   their common face in registers (four LDS adds per cell
- *                   crossed instead of eight), 11, 12, 13 = as 8, 10, 6
- *                   with the footprint summed in 32-bit fixed point (the
- *                   scale of each box and angle bounds every partial sum
- *                   below 2^31; rounding <= 2^-31 of that bound per add; a
- *                   non-finite projection value makes its footprint NaN),
- *                   14 = as 11 with the x-neighbouring corners of a cell
- *                   added as one exact 64-bit integer pair (same rounded
- *                   values and sums as 11, half the LDS adds, twice the
- *                   LDS per workgroup; edges 8, 12, 16 with fixed kernels,
- *                   else as 8).
- *   op 2, tiling:   variant = lab-box edge in voxels, from 4 up to the
- *                   largest edge whose FP64 footprint fits in the 160 KiB
- *                   of LDS (19 for grids of 24^3 voxels and more); rebuilds
+ *                   use, ~32 bytes per run; no atomics, fixed order).
+ *   op 2, tiling:   lab-box edge in voxels: 8, 12 (default) or 16; rebuilds
  *                   the box decomposition (synchronises the device).
- *   op 3, kernels:  1 (default) = use the box kernels specialised to a
- *                   compile-time footprint for edges 8, 12 and 16,
- *                   0 = always use the runtime-stride box kernels.
  *   op 4, order:    order of the segments inside a box for the deposit:
  *                   0 = by ray, 1 = by decreasing length, 2 = by pixel
  *                   parity class (u mod 2, v mod 2) then ray, 3, 4 = by
@@ -248,24 +239,23 @@ vam_status vam_export_rays(vam_geometry_t h, double* out);
  *                   v mod 2), then ray, 11, 12, 13 = order 10, then each
  *                   run of 1024 (11, default), 512 (12) or 2048 (13)
  *                   segments by decreasing length; rebuilds the boxes.
- *   op 5, threads:  workgroup size of the fixed-footprint deposit, 256
- *                   (default) or 512.
- *   op 6, order:    work order of the box kernels, bit 0 forward, bit 1
- *                   deposit: 0 = boxes fastest (all XCDs work on the same
- *                   angles), 1 = XCD-aware (each XCD walks a contiguous
- *                   range of boxes, angles fastest); see also op 8, 9.
+ *   op 5, threads:  workgroup size of the box deposit, 256 (default) or 512.
  *   op 7, order:    as op 4, for the forward projection (default 0).
  *   op 8, 9:        work order of the deposit (8) or forward (9) box
  *                   kernels: 0 = boxes fastest (forward default), 1 =
  *                   XCD-aware with all angles of a box on one XCD, A >= 2 =
  *                   XCD-aware with the angles of a box in blocks of A (up
  *                   to 4096; deposit default 8).
- *   op 10, cache:   1 = the fixed-footprint forward keeps the current
- *                   cell's 8 corner values in registers and reads LDS only
- *                   when a sample enters a new cell, 0 = reads every sample.
- * FP64 accumulators are allocated on first use.  Errors:
- * VAM_ERR_BAD_HANDLE, VAM_ERR_INVALID_ARG for an unknown op or variant. */
+ * A failed rebuild (ops 2, 4, 7) leaves the handle without a box
+ * decomposition: the box kernels then return VAM_ERR_INVALID_ARG until a
+ * rebuild succeeds.  Errors: VAM_ERR_BAD_HANDLE, VAM_ERR_INVALID_ARG for an
+ * unknown op or variant, VAM_ERR_OUT_OF_MEMORY, VAM_ERR_HIP. */
 vam_status vam_set_variant(vam_geometry_t h, int32_t op, int32_t variant);
+
+/* Test hook for error paths: the n-th device allocation the library makes
+ * after this call (n >= 1) fails as if the device were out of memory; n = 0
+ * switches the hook off.  Process-wide, not thread-safe; for tests only. */
+vam_status vam_debug_fail_allocations(int32_t n);
 
 /* Instrumentation: device time (ms) of the main kernel of the last
  * vam_forward_project and of the last vam_back_project on this handle,

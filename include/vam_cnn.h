@@ -51,6 +51,14 @@ int64_t vam_cnn_param_count(vam_cnn_t h);
  * set also clears the Adam moments and step count.  Synchronous. */
 vam_status vam_cnn_set_params(vam_cnn_t h, const float* params);
 vam_status vam_cnn_get_params(vam_cnn_t h, float* params);
+/* Training state for checkpoint and resume: state (host, 3 * param_count
+ * floats) holds the parameters, then Adam's first and second moments, in
+ * the layout above; adam_steps the number of Adam steps taken.  set
+ * restores exactly what get returned, so training resumed from a
+ * checkpoint takes the same steps as training that never stopped.
+ * Synchronous. */
+vam_status vam_cnn_get_state(vam_cnn_t h, float* state, int64_t* adam_steps);
+vam_status vam_cnn_set_state(vam_cnn_t h, const float* state, int64_t adam_steps);
 /* Inference: x [n][2][H][W] -> y [n][H][W] (device, FP32), n <= max_batch. */
 vam_status vam_cnn_forward(vam_cnn_t h, const float* x, int32_t n, float* y, hipStream_t stream);
 /* Loss and gradients of L = mean over the n H W pixels of (y - t)^2 s1^2

@@ -28,17 +28,12 @@ VAM_TELECENTRIC, VAM_THIN_LENS = 0, 1
 VAM_NO_FRESNEL = 1
 RAY_FIELDS = 12
 
-OP_FORWARD, OP_DEPOSIT = 0, 1
-FWD_DEFAULT, FWD_PLAIN, FWD_BOX, FWD_TUNED = 0, 1, 2, 3
-ADJ_DEFAULT, ADJ_SCATTER_DIRECT, ADJ_SCATTER_AGGREGATED, ADJ_SCATTER_FP64 = 0, 1, 2, 3
-ADJ_TUNED_FP32, ADJ_TUNED_FP64 = 4, 5
-ADJ_BOX_FP64, ADJ_BOX_FP32, ADJ_BOX_AGG = 6, 7, 8
-ADJ_GATHER = 9
-ADJ_BOX_SHARED = 10
-ADJ_BOX_INT_AGG, ADJ_BOX_INT_SHARED, ADJ_BOX_INT = 11, 12, 13
-ADJ_BOX_INT_PAIR = 14
-OP_BOX_EDGE, OP_FIXED_KERNELS, OP_SEG_ORDER, OP_DEPOSIT_THREADS, OP_WORK_ORDER = 2, 3, 4, 5, 6
-OP_SEG_ORDER_FWD = 7
+# vam_set_variant operators and variants (include/vam.h)
+OP_FORWARD, OP_DEPOSIT, OP_BOX_EDGE, OP_SEG_ORDER, OP_DEPOSIT_THREADS = 0, 1, 2, 4, 5
+OP_SEG_ORDER_FWD, OP_ANGLE_BLOCK_DEPOSIT, OP_ANGLE_BLOCK_FORWARD = 7, 8, 9
+FWD_DEFAULT, FWD_RAY = 0, 1
+ADJ_DEFAULT, ADJ_RAY, ADJ_GATHER = 0, 1, 2
+BOX_EDGES = (8, 12, 16)
 
 
 class VamError(RuntimeError):
@@ -91,7 +86,8 @@ def lib():
             "vam_destroy_geometry": [_P],
             "vam_forward_project": [_P, _P, _I32, _P, _I32, _I32, _I32, _P],
             "vam_back_project": [_P, _P, _I32, _P, _I32, _I32, _I32, _P],
-            "vam_optimize_step": [_P, _P, _P, _P, ctypes.POINTER(OptParams), _DP, _P],
+            "vam_optimize_step": [_P, _P, _P, _I32, _P, ctypes.POINTER(OptParams), _DP, _P],
+            "vam_debug_fail_allocations": [_I32],
             "vam_ray_table_stats": [_P, _I64P, _I64P],
             "vam_export_rays": [_P, _DP],
             "vam_set_variant": [_P, _I32, _I32],
@@ -104,6 +100,8 @@ def lib():
             "vam_cnn_set_params": [_P, _P],
             "vam_cnn_get_params": [_P, _P],
             "vam_cnn_get_grads": [_P, _P],
+            "vam_cnn_get_state": [_P, _P, _I64P],
+            "vam_cnn_set_state": [_P, _P, ctypes.c_int64],
             "vam_cnn_forward": [_P, _P, _I32, _P, _P],
             "vam_cnn_loss_grad": [_P, _P, _P, _I32, _DP, _P],
             "vam_cnn_adam_step": [_P, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, _P],
@@ -253,9 +251,6 @@ class Geometry:
     def set_forward_variant(self, variant):
         _check(lib().vam_set_variant(self.handle, OP_FORWARD, int(variant)))
 
-    def set_fixed_kernels(self, on):
-        _check(lib().vam_set_variant(self.handle, OP_FIXED_KERNELS, int(bool(on))))
-
     def set_segment_order(self, order, forward=False):
         """Rebuild the box decomposition with segment order 0 (ray),
         1 (length), 2 (pixel parity class), 3, 4 (pixel class mod 3, 4),
@@ -266,25 +261,20 @@ class Geometry:
         deposit (or forward)."""
         _check(lib().vam_set_variant(self.handle, OP_SEG_ORDER_FWD if forward else OP_SEG_ORDER, int(order)))
 
-    def set_work_order(self, xcd_forward, xcd_deposit):
-        _check(lib().vam_set_variant(self.handle, OP_WORK_ORDER, int(bool(xcd_forward)) | (int(bool(xcd_deposit)) << 1)))
-
     def set_angle_blocks(self, deposit=None, forward=None):
         """Work order with the angles of a box in blocks (0: boxes fastest,
         1: all angles of a box on one XCD, A >= 2: blocks of A angles)."""
         if deposit is not None:
-            _check(lib().vam_set_variant(self.handle, 8, int(deposit)))
+            _check(lib().vam_set_variant(self.handle, OP_ANGLE_BLOCK_DEPOSIT, int(deposit)))
         if forward is not None:
-            _check(lib().vam_set_variant(self.handle, 9, int(forward)))
-
-    def set_forward_cache(self, on):
-        _check(lib().vam_set_variant(self.handle, 10, int(bool(on))))
+            _check(lib().vam_set_variant(self.handle, OP_ANGLE_BLOCK_FORWARD, int(forward)))
 
     def set_deposit_threads(self, n):
         _check(lib().vam_set_variant(self.handle, OP_DEPOSIT_THREADS, int(n)))
 
     def set_box_edge(self, edge):
-        """Rebuild the lab-box decomposition with boxes of `edge` voxels."""
+        """Rebuild the lab-box decomposition with boxes of `edge` voxels
+        (8, 12 or 16)."""
         _check(lib().vam_set_variant(self.handle, OP_BOX_EDGE, int(edge)))
 
     def forward(self, vol, out=None, angle_begin=0, angle_count=None, out_dtype=None, stream=None):
@@ -320,19 +310,26 @@ class Geometry:
     def optimize_step(self, target, proj, threshold=0.8, sharpness=20.0, lr=1.0, clamp_nonneg=True,
                       dose=None, want_loss=True, stream=None):
         """One projected gradient step on the dose-threshold loss; updates
-        proj in place and returns the loss before the update (or None)."""
+        proj (float32, bfloat16 or float16, as stored) in place and returns
+        the loss before the update (or None)."""
         torch = _torch()
         _need_device_tensor(target, "target", self.vol_shape, (torch.float32,))
-        _need_device_tensor(proj, "proj", self.proj_shape, (torch.float32,))
+        _need_device_tensor(proj, "proj", self.proj_shape, (torch.float32, torch.bfloat16, torch.float16))
         if dose is not None:
             _need_device_tensor(dose, "dose", self.vol_shape, (torch.float32,))
         prm = OptParams(float(threshold), float(sharpness), float(lr), int(bool(clamp_nonneg)))
         loss = ctypes.c_double()
-        _check(lib().vam_optimize_step(self.handle, target.data_ptr(), proj.data_ptr(),
+        _check(lib().vam_optimize_step(self.handle, target.data_ptr(), proj.data_ptr(), _dtype_code(proj.dtype),
                                        dose.data_ptr() if dose is not None else None,
                                        ctypes.byref(prm), ctypes.byref(loss) if want_loss else None,
                                        _stream_ptr(stream)))
         return loss.value if want_loss else None
+
+
+def debug_fail_allocations(n):
+    """Make the n-th following device allocation of the library fail (tests
+    of the error paths); 0 switches this off."""
+    _check(lib().vam_debug_fail_allocations(int(n)))
 
 
 def ramlak_filter(proj, pitch=1.0, clip_negative=True, out=None, stream=None):
@@ -415,6 +412,20 @@ class Cnn:
         a = np.empty(self.n_params, dtype=np.float32)
         _check(lib().vam_cnn_get_params(self.handle, a.ctypes.data))
         return a
+
+    def get_state(self):
+        """(parameters, Adam first moments, Adam second moments) as one FP32
+        array of 3 * n_params, and the Adam step count: a checkpoint."""
+        a = np.empty(3 * self.n_params, dtype=np.float32)
+        t = ctypes.c_int64()
+        _check(lib().vam_cnn_get_state(self.handle, a.ctypes.data, ctypes.byref(t)))
+        return a, t.value
+
+    def set_state(self, state, adam_steps):
+        a = np.ascontiguousarray(state, dtype=np.float32)
+        if a.size != 3 * self.n_params:
+            raise ValueError("expected %d state values, got %d" % (3 * self.n_params, a.size))
+        _check(lib().vam_cnn_set_state(self.handle, a.ctypes.data, int(adam_steps)))
 
     def grads(self):
         a = np.empty(self.n_params, dtype=np.float32)

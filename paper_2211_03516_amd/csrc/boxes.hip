@@ -1,46 +1,57 @@
-// Lab-box tiling of the dose deposit (Sec. 2.5 of Webber et al.).
+// Lab-box tiling of the forward projection (Sec. 2.4 of Webber et al.) and
+// of the dose deposit (Sec. 2.5).
 //
 // The vial turns about +z, so every ray sample has a fixed position in the
 // lab frame; only its volume-frame position depends on the angle.  At setup
 // the resin samples of every ray are cut into segments, one per lab-frame
-// box of B^3 voxels that they cross.  The deposit then runs one workgroup
-// per (box, angle): the box, rotated into the volume frame, covers a small
-// footprint of the padded grid (at most ~(B sqrt 2 + 3)^2 (B + 2) cells),
-// which the workgroup accumulates in LDS with LDS atomics while it marches
+// box of B^3 voxels that they cross, and each segment is stored as a compact
+// record: its first sample's lab position relative to the box, its
+// direction, its sample count and the attenuated weight of its first sample.
+// Both operators then run one workgroup per (box, angle): the box, rotated
+// into the volume frame, covers a small footprint of the padded grid (at
+// most ~(B sqrt 2 + 3)^2 (B + 2) cells), which the workgroup stages in LDS
+// (forward: the volume; deposit: a fixed-point accumulator) while it marches
 // all segments of the box -- about 40 samples per voxel at the full-optics
-// workload, i.e. ~320 corner deposits per cell -- and then adds to the
-// global FP64 accumulator once per cell.  The per-sample work (position,
-// weights, attenuation) is the same as in the ray-driven kernels; only the
-// place the eight corner deposits land changes, from global atomics to LDS.
+// workload.  The per-sample work (position, trilinear weights of Sec. 2.2,
+// Beer-Lambert attenuation) is the same as in the ray-driven kernels; only
+// the place where the eight corner values are read or added changes, from
+// global memory to LDS.
 
 #include <algorithm>
 #include <cmath>
 #include <type_traits>
-#include <vector>
 
 #include "vam_internal.h"
 
 namespace vam {
 
-constexpr int kBox = 12;
-constexpr int kMaxLdsBytes = 160 * 1024;  // LDS per CU on gfx950
+constexpr int kBox = 12;  // default lab box edge (fastest measured for both operators)
+constexpr int kXcds = 8;  // XCDs of an MI355X; workgroup L of a launch runs on XCD L mod 8
 
-// Cells of the largest rotated-box footprint for box edge B in a padded
-// grid of px x py x pz: a rotated box spans at most B sqrt 2 cells in x and
-// y and B in z; the footprint adds the rounding margin and the +1 corner.
+// Compile-time footprints for the supported box edges: row pitch WXY, WZ
+// slices (the largest footprint of a rotated box: extent B(|cos| + |sin|) <=
+// B sqrt 2 cells in x and y plus the rounding margin and the +1 corner, B + 2
+// in z).
+template <int B>
+struct Fixed;
+template <>
+struct Fixed<8> {
+  static constexpr int WXY = 14, WZ = 10;
+};
+template <>
+struct Fixed<12> {
+  static constexpr int WXY = 19, WZ = 14;
+};
+template <>
+struct Fixed<16> {
+  static constexpr int WXY = 25, WZ = 18;
+};
+
+bool supported_box_edge(int B) { return B == 8 || B == 12 || B == 16; }
+
 static void footprint_bound(int B, int px, int py, int pz, int& wxy, int& wz) {
   wxy = std::min((int)std::floor(B * std::sqrt(2.0) + 3.02), std::max(px, py));
   wz = std::min(B + 2, pz);
-}
-
-int max_box_edge(const vam_geometry* h) {
-  int best = 4;
-  for (int B = 4; B <= 64; ++B) {
-    int wxy, wz;
-    footprint_bound(B, h->px, h->py, h->pz, wxy, wz);
-    if ((int64_t)wxy * wxy * wz * 8 <= kMaxLdsBytes) best = B;
-  }
-  return best;
 }
 
 __device__ inline int box_of(const BoxGrid& G, double x, double y, double z) {
@@ -53,9 +64,10 @@ __device__ inline int box_of(const BoxGrid& G, double x, double y, double z) {
   return (bz * G.nby + by) * G.nbx + bx;
 }
 
-// Walk the z-clipped samples of every ray in the lab frame (FP64) and call
-// emit(box, first k, count, rank) once per maximal run of samples in one
-// box; rank numbers the runs of a ray from 0 in marching order.
+// Walk the z-clipped samples of a ray in the lab frame (FP64, sample k at
+// e + (k + 1/2) step d) and call emit(box, first k, count, rank) once per
+// maximal run of samples in one box; rank numbers the runs of a ray from 0
+// in marching order.
 template <class F>
 __device__ inline void walk_segments(const BoxGrid& G, const RayRec& R, const double* o, double step,
                                      F emit) {
@@ -95,93 +107,197 @@ __global__ void k_seg_fill(BoxGrid G, const RayRec* rays, const double* ray64, i
   });
 }
 
-void free_boxes(vam_geometry* h) {
-  void* ptrs[] = {h->segs, h->segs_fwd, h->box_begin, h->box_id, h->ray_nseg, h->seg_part};
-  for (void* p : ptrs)
-    if (p) (void)hipFree(p);
-  h->segs = nullptr;
-  h->segs_fwd = nullptr;
-  h->box_begin = nullptr;
-  h->box_id = nullptr;
-  h->ray_nseg = nullptr;
-  h->seg_part = nullptr;
-  h->n_boxes = 0;
-  h->n_segments = 0;
-  h->max_seg_per_ray = 0;
+// Compact records of the (sorted) segments {ray, first k, count, rank} of
+// every box, one workgroup per box.  The lab position of the segment's
+// middle sample m = (count - 1) / 2 (rounded down) is formed in FP64 and
+// stored relative to the box (x, y from its centre, z from its bottom face),
+// so FP32 keeps it to ~1e-6 voxel, and the kernels step from it by at most
+// half the segment (the rounding of the direction grows with the distance
+// stepped); the weight is (T1 T2 / n_pupil) step exp(-alpha s) at the
+// segment's first sample, rounded once.
+//   pw = (x_m - xc, y_m - yc, z_m - zb, weight), dn = (d_x, d_y, d_z, count),
+//   idx = pixel (deposit) or partial-sum slot rank * n_rays + ray (forward:
+//   lanes marching neighbouring rays write neighbouring slots).
+__global__ void k_seg_pack(BoxGrid G, const int* box_id, const int* box_begin, const int4* segs,
+                           const double* ray64, int n_rays, double step, double alpha, int npix,
+                           int forward, float4* pw, float4* dn, int* idx) {
+  const int b = blockIdx.x;
+  const int box = box_id[b];
+  const int bx = box % G.nbx, by = (box / G.nbx) % G.nby, bz = box / (G.nbx * G.nby);
+  const double xc = G.x0 + (bx + 0.5) * G.B, yc = G.y0 + (by + 0.5) * G.B, zb = G.z0 + (double)bz * G.B;
+  for (int i = box_begin[b] + threadIdx.x; i < box_begin[b + 1]; i += blockDim.x) {
+    const int4 sg = segs[i];
+    const double* o = ray64 + (int64_t)sg.x * kRay64Fields;
+    const double s = (sg.y + 0.5) * step;
+    const double sm = (sg.y + (sg.z - 1) / 2 + 0.5) * step;
+    pw[i] = make_float4((float)(o[0] + sm * o[3] - xc), (float)(o[1] + sm * o[4] - yc),
+                        (float)(o[2] + sm * o[5] - zb), (float)(o[8] * step * exp(-alpha * s)));
+    dn[i] = make_float4((float)o[3], (float)o[4], (float)o[5], __int_as_float(sg.z));
+    idx[i] = forward ? sg.w * n_rays + sg.x : sg.x % npix;
+  }
 }
 
-struct BoxParams {
-  BoxGrid G;
-  int nboxes, na;      // work items of the launch: boxes x angles
-  int xcd;             // 1: XCD-aware work order (see work_item)
-  const int4* segs;
-  const int* box_begin;
-  const int* box_id;
-  int wxy_max, wz_max;
-  int npix;            // n_u * n_v
-  int px, py, pz;
-  double supp_coef;    // integer LDS accumulation: n_supp * step / n_pupil
-};
-
-BoxParams box_params(const vam_geometry* h);
+// ------------------------------------------------- fixed-point bound ------
 
 // Samples per lab-frame unit cell (x, y from -R, padded z), from the same
-// positions the marching kernels use (midpoint + t direction, FP64).
-__global__ void k_lab_count(const RayRec* rays, int64_t n_rays, double step, double x0, int ncx, int ncz,
-                            unsigned* count) {
+// FP64 positions the segment records are made of.
+__global__ void k_lab_count(const RayRec* rays, const double* ray64, int64_t n_rays, double step, double x0,
+                            double z0, int ncx, int ncz, unsigned* count) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= n_rays) return;
   const RayRec R = rays[r];
+  const double* o = ray64 + r * kRay64Fields;
   for (int k = R.k0; k < R.k0 + R.n; ++k) {
-    const double t = ((double)k + 0.5 - 0.5 * (double)R.K) * step;
-    const int ix = min(max((int)floor(R.mx + t * R.dx - x0), 0), ncx - 1);
-    const int iy = min(max((int)floor(R.my + t * R.dy - x0), 0), ncx - 1);
-    const int iz = min(max((int)floor((double)R.gz + t * (double)R.dz), 0), ncz - 1);
+    const double s = (k + 0.5) * step;
+    const int ix = min(max((int)floor(o[0] + s * o[3] - x0), 0), ncx - 1);
+    const int iy = min(max((int)floor(o[1] + s * o[4] - x0), 0), ncx - 1);
+    const int iz = min(max((int)floor(o[2] + s * o[5] - z0), 0), ncz - 1);
     atomicAdd(count + ((int64_t)iz * ncx + iy) * ncx + ix, 1u);
   }
 }
 
-// Largest sample count of any 4 x 4 x 3 block of cells.
-__global__ void k_window_max(const unsigned* count, int ncx, int ncz, unsigned* out) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= (int64_t)ncx * ncx * ncz) return;
-  const int ix = (int)(i % ncx), iy = (int)((i / ncx) % ncx), iz = (int)(i / ((int64_t)ncx * ncx));
-  unsigned sum = 0;
-  for (int dz = 0; dz < 3 && iz + dz < ncz; ++dz)
-    for (int dy = 0; dy < 4 && iy + dy < ncx; ++dy)
-      for (int dx = 0; dx < 4 && ix + dx < ncx; ++dx) sum += count[((int64_t)(iz + dz) * ncx + iy + dy) * ncx + ix + dx];
-  atomicMax(out, sum);
+// Per-box bound of the fixed-point deposit: the most samples OF THE BOX in
+// any 4 x 4 x 3 block of lab-frame unit cells.  The box's samples are the
+// samples inside its B^3 cells, so that is the largest window sum of the
+// cell counts clipped to the box; a voxel's turned support (a 2 x 2 x 2
+// cube: at most 2 sqrt 2 wide in x and y) always fits in such a block, so
+// at any angle the box adds at most that many samples into one LDS cell.
+// One workgroup per box.
+__global__ void k_box_supp(BoxGrid G, const int* box_id, const unsigned* count, int ncx, int ncz, int* supp) {
+  __shared__ unsigned s_max;
+  if (threadIdx.x == 0) s_max = 0u;
+  __syncthreads();
+  const int box = box_id[blockIdx.x];
+  const int bx = box % G.nbx, by = (box / G.nbx) % G.nby, bz = box / (G.nbx * G.nby);
+  const int x0 = bx * G.B, y0 = by * G.B, z0 = bz * G.B;
+  const int x1 = min(x0 + G.B, ncx), y1 = min(y0 + G.B, ncx), z1 = min(z0 + G.B, ncz);
+  // window anchors (lowest cell) from 3 (x, y) or 2 (z) cells before the box
+  const int nwx = G.B + 3, nwz = G.B + 2;
+  unsigned best = 0;
+  for (int w = threadIdx.x; w < nwx * nwx * nwz; w += blockDim.x) {
+    const int wx = x0 - 3 + w % nwx, wy = y0 - 3 + (w / nwx) % nwx, wz = z0 - 2 + w / (nwx * nwx);
+    unsigned sum = 0;
+    for (int z = max(wz, z0); z < min(wz + 3, z1); ++z)
+      for (int y = max(wy, y0); y < min(wy + 4, y1); ++y)
+        for (int x = max(wx, x0); x < min(wx + 4, x1); ++x) sum += count[((int64_t)z * ncx + y) * ncx + x];
+    best = max(best, sum);
+  }
+  atomicMax(&s_max, best);
+  __syncthreads();
+  if (threadIdx.x == 0) supp[blockIdx.x] = (int)min(max(s_max, 1u), 0x3fffffffu);
 }
 
-// n_supp of the integer LDS deposit (synchronises the stream).
-static vam_status support_bound(vam_geometry* h, hipStream_t s) {
+// Per-box n_supp of the fixed-point deposit (synchronises the stream).
+static vam_status support_bound(vam_geometry* h, const BoxGrid& G, hipStream_t s) {
   const double R = h->desc.r_inner + 1.0;
   const int ncx = (int)std::ceil(2.0 * R), ncz = h->pz;
   const int64_t ncell = (int64_t)ncx * ncx * ncz;
   unsigned* count = nullptr;
-  VAM_HIP_TRY(hipMalloc(&count, (ncell + 1) * sizeof(unsigned)), "allocating lab cell counts");
-  unsigned* out = count + ncell;
-  hipError_t e = hipMemsetAsync(count, 0, (ncell + 1) * sizeof(unsigned), s);
+  VAM_HIP_TRY(dev_alloc((void**)&count, ncell * sizeof(unsigned)), "allocating lab cell counts");
+  hipError_t e = hipMemsetAsync(count, 0, ncell * sizeof(unsigned), s);
   if (e == hipSuccess) {
-    hipLaunchKernelGGL(k_lab_count, dim3((unsigned)((h->n_rays + 255) / 256)), dim3(256), 0, s, h->rays, h->n_rays,
-                       h->desc.step, -R, ncx, ncz, count);
-    hipLaunchKernelGGL(k_window_max, dim3((unsigned)((ncell + 255) / 256)), dim3(256), 0, s, count, ncx, ncz, out);
+    const double z0 = -(0.5 * (h->desc.nz - 1) + kPad);
+    hipLaunchKernelGGL(k_lab_count, dim3((unsigned)((h->n_rays + 255) / 256)), dim3(256), 0, s, h->rays, h->ray64,
+                       h->n_rays, h->desc.step, -R, z0, ncx, ncz, count);
+    if (h->n_boxes > 0)
+      hipLaunchKernelGGL(k_box_supp, dim3((unsigned)h->n_boxes), dim3(256), 0, s, G, h->box_id, count, ncx, ncz,
+                         h->box_supp);
     e = hipGetLastError();
   }
-  unsigned hmax = 0;
-  if (e == hipSuccess) e = hipMemcpyAsync(&hmax, out, sizeof(unsigned), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   (void)hipFree(count);
   if (e != hipSuccess) return hip_check(e, "bounding samples per voxel support");
-  h->n_supp = std::max<int64_t>(hmax, 1);
   return VAM_OK;
 }
 
-vam_status build_boxes(vam_geometry* h, hipStream_t s) {
-  if (h->n_supp == 0) {
-    vam_status st = support_bound(h, s);
-    if (st != VAM_OK) return st;
+// ------------------------------------------------------ decomposition ------
+
+static void free_table(SegTable& t) {
+  void* ptrs[] = {t.pw, t.dn, t.idx};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  t = SegTable{};
+}
+
+void free_boxes(vam_geometry* h) {
+  free_table(h->seg_dep);
+  free_table(h->seg_fwd);
+  void* ptrs[] = {h->box_begin, h->box_id, h->box_supp, h->ray_nseg, h->seg_part};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  h->box_begin = nullptr;
+  h->box_id = nullptr;
+  h->box_supp = nullptr;
+  h->ray_nseg = nullptr;
+  h->seg_part = nullptr;
+  h->seg_part_angles = 0;
+  h->n_boxes = 0;
+  h->n_segments = 0;
+  h->max_seg_per_ray = 0;
+  h->boxes_ready = 0;
+}
+
+static vam_status alloc_table(SegTable& t, int64_t n) {
+  const int64_t m = std::max<int64_t>(n, 1);
+  VAM_HIP_TRY(dev_alloc((void**)&t.pw, m * sizeof(float4)), "allocating segment records");
+  VAM_HIP_TRY(dev_alloc((void**)&t.dn, m * sizeof(float4)), "allocating segment records");
+  VAM_HIP_TRY(dev_alloc((void**)&t.idx, m * sizeof(int)), "allocating segment records");
+  return VAM_OK;
+}
+
+// Order of the segments inside a box, which decides which lanes march
+// together (host sort keys; measured orders, see vam_set_variant op 4):
+//  0: by ray -- neighbouring lanes handle neighbouring pixels;
+//  1: by decreasing length -- lanes of a wave march similar lengths;
+//  2: by pixel parity class (u mod 2, v mod 2), then ray -- the lanes of
+//     a wave handle pixels two apart, whose trilinear stencils are disjoint;
+//  3, 4: the same with classes (u mod m, v mod m), m = 3, 4;
+//  5: by a hash of the ray index (lanes at unrelated positions);
+//  6: by pixel, then pupil sample -- the rays of one pixel, which meet at
+//     the focus plane, go to neighbouring lanes;
+//  7, 8: order 3, then each run of 1024 (7) or 2048 (8) consecutive
+//     segments by decreasing length in steps of two samples (a stable sort:
+//     equal steps keep their class order), so that the 64 lanes of a wave
+//     march similar lengths and the waves of a workgroup get equal shares;
+//  9: by pupil sample, then pixel column u, then row v -- neighbouring
+//     lanes march rays one pixel apart in z, which does not turn;
+//  10: by class (u mod 3, v mod 2), then ray (lanes three pixels apart
+//     along a row, rows two apart);
+//  11, 12, 13: order 10, then each run of 1024 (11), 512 (12) or 2048
+//     (13) consecutive segments by decreasing length.
+static void sort_segments(std::vector<int4>& hs, const std::vector<int>& begin, int order, int nu, int nv,
+                          int np) {
+  auto key = [&](const int4& s, int ord) -> int64_t {
+    const int r = s.x;
+    const int u = r % nu, v = (r / nu) % nv;
+    if (ord == 1) return ((int64_t)(0x7fffffff - s.z) << 32) | (uint32_t)r;
+    if (ord >= 2 && ord <= 4) return ((int64_t)((v % ord) * ord + (u % ord)) << 32) | (uint32_t)r;
+    if (ord == 6) return (int64_t)(r % (nu * nv)) * np + r / (nu * nv);
+    if (ord == 9) return ((int64_t)(r / (nu * nv)) * nu + u) * nv + v;
+    if (ord == 10) return ((int64_t)((v % 2) * 3 + (u % 3)) << 32) | (uint32_t)r;
+    if (ord == 5) {
+      uint64_t x = (uint64_t)r + 0x9e3779b97f4a7c15ull;  // SplitMix64 finaliser
+      x = (x ^ (x >> 30)) * 0xbf58476d1ce4e5b9ull;
+      x = (x ^ (x >> 27)) * 0x94d049bb133111ebull;
+      return (int64_t)((x ^ (x >> 31)) >> 1);
+    }
+    return r;
+  };
+  const int korder = (order == 7 || order == 8) ? 3 : (order >= 11 && order <= 13) ? 10 : order;
+  const int run = (order == 7 || order == 11) ? 1024 : (order == 8 || order == 13) ? 2048 : order == 12 ? 512 : 0;
+  for (size_t i = 0; i + 1 < begin.size(); ++i) {
+    std::sort(hs.begin() + begin[i], hs.begin() + begin[i + 1],
+              [&](const int4& x, const int4& y) { return key(x, korder) < key(y, korder); });
+    for (int64_t g = begin[i]; run && g < begin[i + 1]; g += run)
+      std::stable_sort(hs.begin() + g, hs.begin() + std::min<int64_t>(g + run, begin[i + 1]),
+                       [](const int4& x, const int4& y) { return (x.z >> 1) > (y.z >> 1); });
   }
+}
+
+// Build the decomposition into the handle (everything it allocates is
+// recorded in the handle as soon as it exists, so free_boxes releases it
+// on any failure).  Synchronises the stream.
+static vam_status build_boxes_into(vam_geometry* h, hipStream_t s) {
   const vam_geometry_desc& D = h->desc;
   BoxGrid G;
   G.B = h->box_edge > 0 ? h->box_edge : kBox;
@@ -195,27 +311,30 @@ vam_status build_boxes(vam_geometry* h, hipStream_t s) {
   h->boxes = G;
   const int nb_all = G.nbx * G.nby * G.nbz;
 
+  VAM_HIP_TRY(dev_alloc((void**)&h->ray_nseg, h->n_rays * sizeof(int)), "allocating segment counts");
+  // staging: box counts, offsets and cursors, then the unsorted segments
   int* count = nullptr;
-  int* off = nullptr;
-  VAM_HIP_TRY(hipMalloc(&count, nb_all * sizeof(int)), "allocating box counts");
-  VAM_HIP_TRY(hipMalloc(&off, nb_all * sizeof(int)), "allocating box offsets");
-  VAM_HIP_TRY(hipMalloc(&h->ray_nseg, h->n_rays * sizeof(int)), "allocating segment counts");
+  int4* segs = nullptr;
   auto release = [&]() {
-    (void)hipFree(count);
-    (void)hipFree(off);
+    if (count) (void)hipFree(count);
+    if (segs) (void)hipFree(segs);
+    count = nullptr;
+    segs = nullptr;
   };
-  hipError_t e = hipMemsetAsync(count, 0, nb_all * sizeof(int), s);
-  if (e != hipSuccess) {
-    release();
-    return hip_check(e, "clearing box counts");
-  }
+  hipError_t e = dev_alloc((void**)&count, 2 * (int64_t)nb_all * sizeof(int));
+  if (e != hipSuccess) return hip_check(e, "allocating box counts");
+  int* off = count + nb_all;
+  e = hipMemsetAsync(count, 0, nb_all * sizeof(int), s);
   const int threads = 256;
   const unsigned blocks = (unsigned)((h->n_rays + threads - 1) / threads);
-  hipLaunchKernelGGL(k_seg_count, dim3(blocks), dim3(threads), 0, s, G, h->rays, h->ray64, h->n_rays,
-                     D.step, count, h->ray_nseg);
-  std::vector<int> hc(nb_all);
-  e = hipGetLastError();
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_seg_count, dim3(blocks), dim3(threads), 0, s, G, h->rays, h->ray64, h->n_rays, D.step,
+                       count, h->ray_nseg);
+    e = hipGetLastError();
+  }
+  std::vector<int> hc(nb_all), ns(h->n_rays);
   if (e == hipSuccess) e = hipMemcpyAsync(hc.data(), count, nb_all * sizeof(int), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(ns.data(), h->ray_nseg, h->n_rays * sizeof(int), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) {
     release();
@@ -224,168 +343,140 @@ vam_status build_boxes(vam_geometry* h, hipStream_t s) {
   std::vector<int> hoff(nb_all), begin, ids;
   int64_t total = 0;
   for (int b = 0; b < nb_all; ++b) {
-    hoff[b] = (int)total;
+    hoff[b] = (int)std::min<int64_t>(total, 0x7fffffff);
     if (hc[b] > 0) {
       ids.push_back(b);
-      begin.push_back((int)total);
+      begin.push_back((int)std::min<int64_t>(total, 0x7fffffff));
     }
     total += hc[b];
   }
-  begin.push_back((int)total);
+  begin.push_back((int)std::min<int64_t>(total, 0x7fffffff));
   if (total >= 0x7fffffffLL) {
     release();
     return fail(VAM_ERR_UNSUPPORTED, "more than 2^31 ray segments");
   }
-  h->n_boxes = (int)ids.size();
-  h->n_segments = total;
-  e = hipMalloc(&h->segs, std::max<int64_t>(total, 1) * sizeof(int4));
-  if (e == hipSuccess) e = hipMalloc(&h->box_begin, begin.size() * sizeof(int));
-  if (e == hipSuccess) e = hipMalloc(&h->box_id, std::max<size_t>(ids.size(), 1) * sizeof(int));
+  // forward partial-sum slots rank * n_rays + ray must be 32-bit offsets
+  h->max_seg_per_ray = ns.empty() ? 0 : *std::max_element(ns.begin(), ns.end());
+  if ((int64_t)h->max_seg_per_ray * h->n_rays >= 0x7fffffffLL) {
+    release();
+    return fail(VAM_ERR_UNSUPPORTED, "more than 2^31 forward partial-sum slots per angle");
+  }
+  e = dev_alloc((void**)&segs, std::max<int64_t>(total, 1) * sizeof(int4));
+  if (e == hipSuccess) e = dev_alloc((void**)&h->box_begin, begin.size() * sizeof(int));
+  if (e == hipSuccess) e = dev_alloc((void**)&h->box_id, std::max<size_t>(ids.size(), 1) * sizeof(int));
+  if (e == hipSuccess) e = dev_alloc((void**)&h->box_supp, std::max<size_t>(ids.size(), 1) * sizeof(int));
   if (e == hipSuccess) e = hipMemcpyAsync(off, hoff.data(), nb_all * sizeof(int), hipMemcpyHostToDevice, s);
   if (e == hipSuccess)
     e = hipMemcpyAsync(h->box_begin, begin.data(), begin.size() * sizeof(int), hipMemcpyHostToDevice, s);
   if (e == hipSuccess && !ids.empty())
     e = hipMemcpyAsync(h->box_id, ids.data(), ids.size() * sizeof(int), hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipMemsetAsync(count, 0, nb_all * sizeof(int), s);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_seg_fill, dim3(blocks), dim3(threads), 0, s, G, h->rays, h->ray64, h->n_rays, D.step,
+                       off, count, segs);
+    e = hipGetLastError();
+  }
+  std::vector<int4> hs(std::max<int64_t>(total, 1));
+  if (e == hipSuccess) e = hipMemcpyAsync(hs.data(), segs, total * sizeof(int4), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) {
     release();
-    return hip_check(e, "allocating box segments");
+    return hip_check(e, "filling box segments");
   }
-  hipLaunchKernelGGL(k_seg_fill, dim3(blocks), dim3(threads), 0, s, G, h->rays, h->ray64, h->n_rays, D.step,
-                     off, count, h->segs);
-  e = hipGetLastError();
-  if (e == hipSuccess) e = hipStreamSynchronize(s);
-  release();
-  if (e != hipSuccess) return hip_check(e, "filling box segments");
-  // Order each box's segments, once for the deposit (h->segs) and once for
-  // the forward projection (h->segs_fwd); sorting also makes the order
-  // independent of the scheduling of the fill kernel:
-  //  0: by ray -- neighbouring lanes handle neighbouring pixels;
-  //  1: by decreasing length -- lanes of a wave march similar lengths;
-  //  2: by pixel parity class (u mod 2, v mod 2), then ray -- the lanes of
-  //     a wave handle pixels two apart, whose trilinear stencils are disjoint;
-  //  3, 4: the same with classes (u mod m, v mod m), m = 3, 4;
-  //  5: by a hash of the ray index (lanes at unrelated positions);
-  //  6: by pixel, then pupil sample -- the rays of one pixel, which meet at
-  //     the focus plane, go to neighbouring lanes;
-  //  7, 8: order 3, then each run of 1024 (7) or 2048 (8) consecutive
-  //     segments by decreasing length in steps of two samples (a stable sort:
-  //     equal steps keep their class order; exact lengths measured 1.5 %
-  //     slower), so that the 64 lanes of a wave march similar lengths and
-  //     the four waves of a workgroup get equal shares
-  //     (the same runs on order 0 make the forward slower: 180 -> 187 ms);
-  //  9: by pupil sample, then pixel column u, then row v -- neighbouring
-  //     lanes march rays one pixel apart in z, which does not turn;
-  //  10: by class (u mod 3, v mod 2), then ray (lanes three pixels apart
-  //     along a row, rows two apart);
-  //  11, 12, 13: order 10, then each run of 1024 (11), 512 (12) or 2048
-  //     (13) consecutive segments by decreasing length.
+  h->n_boxes = (int)ids.size();
+  h->n_segments = total;
   {
-    std::vector<int4> hs(std::max<int64_t>(total, 1));
-    e = hipMemcpy(hs.data(), h->segs, total * sizeof(int4), hipMemcpyDeviceToHost);
-    if (e != hipSuccess) return hip_check(e, "reading box segments");
-    const int nu = D.n_u, nv = D.n_v;
-    auto sort_by = [&](int order) {
-      auto key = [&](const int4& s, int order) -> int64_t {
-        const int r = s.x;
-        const int u = r % nu, v = (r / nu) % nv;
-        if (order == 1) return ((int64_t)(0x7fff - s.z) << 32) | (uint32_t)r;
-        if (order >= 2 && order <= 4) {
-          const int m = order;
-          return ((int64_t)((v % m) * m + (u % m)) << 32) | (uint32_t)r;
-        }
-        if (order == 6) return (int64_t)(r % (nu * nv)) * D.n_pupil + r / (nu * nv);
-        if (order == 9) return ((int64_t)(r / (nu * nv)) * nu + u) * nv + v;
-        if (order == 10) return ((int64_t)((v % 2) * 3 + (u % 3)) << 32) | (uint32_t)r;
-        if (order == 5) {
-          uint64_t x = (uint64_t)r + 0x9e3779b97f4a7c15ull;  // SplitMix64 finaliser
-          x = (x ^ (x >> 30)) * 0xbf58476d1ce4e5b9ull;
-          x = (x ^ (x >> 27)) * 0x94d049bb133111ebull;
-          return (int64_t)((x ^ (x >> 31)) >> 1);
-        }
-        return r;
-      };
-      const int korder = (order == 7 || order == 8) ? 3 : (order >= 11 && order <= 13) ? 10 : order;
-      const int run = (order == 7 || order == 11)   ? 1024
-                      : (order == 8 || order == 13) ? 2048
-                      : order == 12                 ? 512
-                                                    : 0;
-      for (size_t i = 0; i + 1 < begin.size(); ++i) {
-        std::sort(hs.begin() + begin[i], hs.begin() + begin[i + 1],
-                  [&](const int4& x, const int4& y) { return key(x, korder) < key(y, korder); });
-        for (int64_t g = begin[i]; run && g < begin[i + 1]; g += run)
-          std::stable_sort(hs.begin() + g, hs.begin() + std::min<int64_t>(g + run, begin[i + 1]),
-                           [](const int4& x, const int4& y) { return (x.z >> 1) > (y.z >> 1); });
-      }
-    };
-    e = hipMalloc(&h->segs_fwd, std::max<int64_t>(total, 1) * sizeof(int4));
-    if (e != hipSuccess) return hip_check(e, "allocating forward segments");
-    sort_by(h->seg_order_fwd);
-    e = hipMemcpy(h->segs_fwd, hs.data(), total * sizeof(int4), hipMemcpyHostToDevice);
-    if (e != hipSuccess) return hip_check(e, "writing forward segments");
-    sort_by(h->seg_order);
-    e = hipMemcpy(h->segs, hs.data(), total * sizeof(int4), hipMemcpyHostToDevice);
-    if (e != hipSuccess) return hip_check(e, "writing box segments");
-    std::vector<int> ns(h->n_rays);
-    e = hipMemcpy(ns.data(), h->ray_nseg, h->n_rays * sizeof(int), hipMemcpyDeviceToHost);
-    if (e != hipSuccess) return hip_check(e, "reading segment counts");
-    h->max_seg_per_ray = ns.empty() ? 0 : *std::max_element(ns.begin(), ns.end());
+    vam_status st = support_bound(h, G, s);
+    if (st != VAM_OK) {
+      release();
+      return st;
+    }
   }
-  // largest footprint of a rotated box: extent B(|cos| + |sin|) <= B sqrt 2
-  // in x and y, B in z, plus the rounding margin and the +1 corner
-  const BoxParams Bp = box_params(h);
-  h->box_cells = Bp.wxy_max * Bp.wxy_max * Bp.wz_max;
+  // both orders, each packed into compact records (the sort also makes the
+  // order independent of the scheduling of the fill kernel)
+  const int npix = D.n_u * D.n_v;
+  for (int fwd = 0; fwd < 2; ++fwd) {
+    SegTable& t = fwd ? h->seg_fwd : h->seg_dep;
+    vam_status st = alloc_table(t, total);
+    if (st != VAM_OK) {
+      release();
+      return st;
+    }
+    sort_segments(hs, begin, fwd ? h->seg_order_fwd : h->seg_order, D.n_u, D.n_v, D.n_pupil);
+    e = hipMemcpyAsync(segs, hs.data(), total * sizeof(int4), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && h->n_boxes > 0) {
+      hipLaunchKernelGGL(k_seg_pack, dim3((unsigned)h->n_boxes), dim3(256), 0, s, G, h->box_id, h->box_begin, segs,
+                         h->ray64, (int)h->n_rays, D.step, D.alpha, npix, fwd, t.pw, t.dn, t.idx);
+      e = hipGetLastError();
+    }
+    // the host copy is re-sorted next: wait for the upload
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+      release();
+      return hip_check(e, "packing box segments");
+    }
+  }
+  release();
+  int wxy, wz;
+  footprint_bound(G.B, h->px, h->py, h->pz, wxy, wz);
+  h->box_cells = wxy * wxy * wz;
   return VAM_OK;
 }
 
-// --------------------------------------------------------------- deposit --
-
-
-
-template <typename PT>
-__device__ inline float load_p(const PT* p, int64_t i);
-template <>
-__device__ inline float load_p<float>(const float* p, int64_t i) { return p[i]; }
-template <>
-__device__ inline float load_p<uint16_t>(const uint16_t* p, int64_t i) {
-  return __uint_as_float((uint32_t)p[i] << 16);
-}
-template <>
-__device__ inline float load_p<__half>(const __half* p, int64_t i) { return __half2float(p[i]); }
-
-
-__device__ inline void store_proj(float* p, int64_t i, float x) { p[i] = x; }
-__device__ inline void store_proj(uint16_t* p, int64_t i, float x) {
-  uint32_t u = __float_as_uint(x);
-  if ((u & 0x7fffffffu) > 0x7f800000u) {
-    p[i] = (uint16_t)((u >> 16) | 0x40u);
-  } else {
-    u += 0x7fffu + ((u >> 16) & 1u);
-    p[i] = (uint16_t)(u >> 16);
+vam_status build_boxes(vam_geometry* h, hipStream_t s) {
+  free_boxes(h);
+  const vam_status st = build_boxes_into(h, s);
+  if (st != VAM_OK) {
+    free_boxes(h);  // nothing half-built stays behind; boxes_ready stays 0
+    return st;
   }
+  h->boxes_ready = 1;
+  return VAM_OK;
 }
-__device__ inline void store_proj(__half* p, int64_t i, float x) { p[i] = __float2half_rn(x); }
 
+// ---------------------------------------------------------- launch data ----
 
-// XCD-aware work order.  Workgroups of a launch are handed to the 8 XCDs
-// round-robin (workgroup L runs on XCD L mod 8), each XCD with its own L2.
-// Work item w = (box, angle) is numbered box-major, angle-minor; XCD x takes
-// the contiguous range [x per, (x + 1) per) in order.  The workgroups in
-// flight on one XCD then share one or two boxes at neighbouring angles, so
-// the box's segment and ray records and its volume footprint are fetched
-// from HBM once and reused from that XCD's L2.
-constexpr int kXcds = 8;
+struct BoxParams {
+  BoxGrid G;
+  int nboxes, na;      // work items of the launch: boxes x angles
+  int xcd;             // work order (see work_item)
+  SegTable seg;
+  const int* box_begin;
+  const int* box_id;
+  const int* box_supp; // fixed-point deposit: per-box n_supp
+  int wxy_max, wz_max;
+  int npix;            // n_u * n_v
+  int px, py, pz;
+  double w_coef;       // step / n_pupil: no sample weight exceeds it times |P|
+};
+
+static BoxParams box_params(const vam_geometry* h, const SegTable& t, int na, int xcd) {
+  BoxParams Bp;
+  Bp.G = h->boxes;
+  Bp.nboxes = h->n_boxes;
+  Bp.na = na;
+  Bp.xcd = xcd;
+  Bp.seg = t;
+  Bp.box_begin = h->box_begin;
+  Bp.box_id = h->box_id;
+  Bp.box_supp = h->box_supp;
+  footprint_bound(h->boxes.B, h->px, h->py, h->pz, Bp.wxy_max, Bp.wz_max);
+  Bp.npix = h->desc.n_u * h->desc.n_v;
+  Bp.px = h->px;
+  Bp.py = h->py;
+  Bp.pz = h->pz;
+  Bp.w_coef = h->desc.step / h->desc.n_pupil;
+  return Bp;
+}
 
 // Work order of the (box, angle) workgroups.
 //   xcd = 0: boxes fastest, every XCD on the same angles;
 //   xcd = 1: each XCD takes a contiguous range of (box, all angles) items, so
-//            a box's segment and ray records are reused from that XCD's L2
-//            across all angles;
+//            a box's segment records are reused from that XCD's L2 across
+//            all angles;
 //   xcd = A >= 2: the same, with the angles in blocks of A: a box's records
 //            are reused across A angles while at most A workgroups of one box
 //            flush into the same dose cells at a time.
-// Workgroups are dispatched to the XCDs round-robin, so workgroup L runs on
-// XCD L mod 8.
 __device__ inline bool work_item(int nboxes, int na, int xcd, int& b, int& a) {
   if (!xcd) {
     const int64_t L = blockIdx.x;
@@ -416,9 +507,11 @@ static inline dim3 work_grid(int nboxes, int na, int xcd) {
   return dim3((unsigned)(((W + kXcds - 1) / kXcds) * kXcds));
 }
 
-// Rotated-box footprint [X0, X1) x [Y0, Y1) x [Z0, Z1) in padded grid cells.
+// Rotated-box footprint [X0, X0 + WX) x [Y0, Y0 + WY) x [Z0, Z0 + WZ) in
+// padded grid cells, and the box's centre in footprint coordinates.
 struct Foot {
   int X0, Y0, Z0, WX, WY, WZ;
+  float cx, cy, zoff;  // box centre (x, y) and bottom face (z) in footprint cells
 };
 
 __device__ inline Foot footprint(const BoxParams& Bp, int box, double c, double s, double cx, double cy) {
@@ -446,180 +539,105 @@ __device__ inline Foot footprint(const BoxParams& Bp, int box, double c, double 
   range(gymin, gymax, Bp.py, Bp.wxy_max, f.Y0, f.WY);
   // z does not turn and the boxes sit on whole cells: the box's samples have
   // z in [bz B, (bz + 1) B) up to the FP32 rounding of their positions, so
-  // the footprint starts at bz B (a sample a rounding error below is clamped
-  // onto it) and ends one cell above the last corner
+  // the footprint starts at bz B and ends one cell above the last corner
   f.Z0 = min(max(bz * G.B, 0), Bp.pz - 2);
   const int zhi = min(min((bz + 1) * G.B + 2, Bp.pz), f.Z0 + Bp.wz_max);
   f.WZ = max(zhi, f.Z0 + 2) - f.Z0;
+  const double xc = xa + 0.5 * G.B, yc = ya + 0.5 * G.B;
+  f.cx = (float)(c * xc + s * yc + cx - f.X0);
+  f.cy = (float)(-s * xc + c * yc + cy - f.Y0);
+  f.zoff = (float)(bz * G.B - f.Z0);
   return f;
 }
 
-// LT is the LDS accumulator type.  FP64: gfx950 executes LDS FP64 atomic
-// adds ~20x faster than FP32 ones (measured 7.7 vs 0.33 lanes per clock per
-// CU), and the partial sums keep FP64 precision.  AGG keeps the 8 corner
-// sums of consecutive samples in one cell in registers and adds them to LDS
-// when the cell changes.
-template <typename PT, typename LT, bool AGG>
-__global__ __launch_bounds__(256) void k_back_box(MarchParams P, BoxParams Bp, const PT* __restrict__ proj,
-                                                  double* __restrict__ dose) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  LT* acc = reinterpret_cast<LT*>(smem);
-  int b, a;
-  if (!work_item(Bp.nboxes, Bp.na, Bp.xcd, b, a)) return;
-  const int box = Bp.box_id[b];
-  const double2 cs = P.cs[P.a0 + a];
-  const Foot f = footprint(Bp, box, cs.x, cs.y, P.cx, P.cy);
-  const int ncell = f.WX * f.WY * f.WZ;
-  for (int i = threadIdx.x; i < ncell; i += blockDim.x) acc[i] = (LT)0;
-  __syncthreads();
-
-  // positions are clamped into the footprint (they lie inside it up to
-  // rounding), so every LDS index is in range
-  const float lox = (float)f.X0, hix = (float)(f.X0 + f.WX) - 1.001f;
-  const float loy = (float)f.Y0, hiy = (float)(f.Y0 + f.WY) - 1.001f;
-  const float loz = (float)f.Z0, hiz = (float)(f.Z0 + f.WZ) - 1.001f;
-  const int sy = f.WX, sz = f.WX * f.WY;
-  const int64_t pbase = (int64_t)a * Bp.npix;
-  const int s_end = Bp.box_begin[b + 1];
-  for (int si = Bp.box_begin[b] + threadIdx.x; si < s_end; si += blockDim.x) {
-    const int4 sg = Bp.segs[si];
-    const int r = sg.x, kb = sg.y, cnt = sg.z;
-    const float pv = load_p(proj, pbase + r % Bp.npix);
-    if (pv == 0.0f) continue;
-    const RayRec R = P.rays[r];
-    const float gx = (float)(cs.x * R.mx + cs.y * R.my + P.cx);
-    const float gy = (float)(-cs.y * R.mx + cs.x * R.my + P.cy);
-    const float dx = (float)(cs.x * R.dx + cs.y * R.dy);
-    const float dy = (float)(-cs.y * R.dx + cs.x * R.dy);
-    const float tb = fmaf((float)(kb - R.k0), P.step, R.t0);
-    float e = R.cw * pv * __builtin_amdgcn_exp2f(P.nb * tb);
-    float kf = 0.0f;
-    int cur = -1;
-    float w[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    for (int k = 0; k < cnt; ++k, kf += 1.0f) {
-      const float t = fmaf(kf, P.step, tb);
-      const float x = __builtin_amdgcn_fmed3f(fmaf(t, dx, gx), lox, hix);
-      const float y = __builtin_amdgcn_fmed3f(fmaf(t, dy, gy), loy, hiy);
-      const float z = __builtin_amdgcn_fmed3f(fmaf(t, R.dz, R.gz), loz, hiz);
-      const float fx = __builtin_amdgcn_fractf(x), fy = __builtin_amdgcn_fractf(y),
-                  fz = __builtin_amdgcn_fractf(z);
-      const int i = ((int)z - f.Z0) * sz + ((int)y - f.Y0) * sy + ((int)x - f.X0);
-      const float z1 = e * fz, z0 = e - z1;
-      const float y01 = z0 * fy, y00 = z0 - y01;
-      const float y11 = z1 * fy, y10 = z1 - y11;
-      const float q[8] = {y00 - y00 * fx, y00 * fx, y01 - y01 * fx, y01 * fx,
-                          y10 - y10 * fx, y10 * fx, y11 - y11 * fx, y11 * fx};
-      if (AGG) {
-        if (i != cur) {
-          if (cur >= 0) {
-            LT* p = acc + cur;
-            atomicAdd(p, (LT)w[0]);
-            atomicAdd(p + 1, (LT)w[1]);
-            atomicAdd(p + sy, (LT)w[2]);
-            atomicAdd(p + sy + 1, (LT)w[3]);
-            atomicAdd(p + sz, (LT)w[4]);
-            atomicAdd(p + sz + 1, (LT)w[5]);
-            atomicAdd(p + sz + sy, (LT)w[6]);
-            atomicAdd(p + sz + sy + 1, (LT)w[7]);
-          }
-          cur = i;
-#pragma unroll
-          for (int c = 0; c < 8; ++c) w[c] = q[c];
-        } else {
-#pragma unroll
-          for (int c = 0; c < 8; ++c) w[c] += q[c];
-        }
-      } else {
-        LT* p = acc + i;
-        atomicAdd(p, (LT)q[0]);
-        atomicAdd(p + 1, (LT)q[1]);
-        atomicAdd(p + sy, (LT)q[2]);
-        atomicAdd(p + sy + 1, (LT)q[3]);
-        atomicAdd(p + sz, (LT)q[4]);
-        atomicAdd(p + sz + 1, (LT)q[5]);
-        atomicAdd(p + sz + sy, (LT)q[6]);
-        atomicAdd(p + sz + sy + 1, (LT)q[7]);
-      }
-      e = fmaf(e, P.r_hi, e * P.r_lo);
-    }
-    if (AGG && cur >= 0) {
-      LT* p = acc + cur;
-      atomicAdd(p, (LT)w[0]);
-      atomicAdd(p + 1, (LT)w[1]);
-      atomicAdd(p + sy, (LT)w[2]);
-      atomicAdd(p + sy + 1, (LT)w[3]);
-      atomicAdd(p + sz, (LT)w[4]);
-      atomicAdd(p + sz + 1, (LT)w[5]);
-      atomicAdd(p + sz + sy, (LT)w[6]);
-      atomicAdd(p + sz + sy + 1, (LT)w[7]);
-    }
-  }
-  __syncthreads();
-  // one global FP64 add per touched cell
-  const int plane = f.WX * f.WY;
-  for (int i = threadIdx.x; i < ncell; i += blockDim.x) {
-    const LT v = acc[i];
-    if (v == (LT)0) continue;
-    const int z = i / plane, rem = i - z * plane, y = rem / f.WX, x = rem - y * f.WX;
-    const int64_t gi = ((int64_t)(f.Z0 + z) * Bp.py + (f.Y0 + y)) * Bp.px + (f.X0 + x);
-    unsafeAtomicAdd(dose + gi, (double)v);
-  }
-}
-
-
-// ------------------------------------------ fixed-footprint kernels ------
-//
-// The same two kernels with the LDS footprint laid out at compile-time
-// strides for a given box edge B (row pitch WXY, slice pitch WXY^2, WZ
-// slices, the largest footprint of a rotated box).  Corner offsets become
-// immediates, index arithmetic uses 24-bit multiplies by constants, and the
-// per-segment origin is formed in FP64 and rounded once:
-//   p_k = P0 + k D,  P0 = g_mid + t_first d - footprint origin,  D = step d.
-
-template <int B>
-struct Fixed;
-template <>
-struct Fixed<8> {
-  static constexpr int WXY = 14, WZ = 10;
-};
-template <>
-struct Fixed<12> {
-  static constexpr int WXY = 19, WZ = 14;
-};
-template <>
-struct Fixed<16> {
-  static constexpr int WXY = 25, WZ = 18;
-};
-static_assert(Fixed<8>::WZ == 8 + 2 && Fixed<12>::WZ == 12 + 2 && Fixed<16>::WZ == 16 + 2,
-              "fixed footprints must match footprint_bound");
-
-struct SegStart {
-  float px, py, pz;   // first sample, footprint-local cell coordinates
+// Middle sample and step of a segment in footprint cells at angle (c, s);
+// sample k of the segment (k = 0 .. count - 1) is at p + (k - m) d.
+struct SegPos {
+  float px, py, pz;   // middle sample m = (count - 1) / 2, rounded down
   float dx, dy, dz;   // step between samples
-  float tb;           // t of the first sample
+  float k0, k1;       // first and last sample relative to m: -m and count - 1 - m
 };
 
-__device__ inline SegStart seg_start(const MarchParams& P, const RayRec& R, double c, double s, const Foot& f,
-                                     int kb) {
-  const double tb = ((double)kb + 0.5 - 0.5 * (double)R.K) * (double)P.step;
-  const double ddx = c * R.dx + s * R.dy, ddy = -s * R.dx + c * R.dy;
-  SegStart g;
-  g.px = (float)(c * R.mx + s * R.my + P.cx - f.X0 + tb * ddx);
-  g.py = (float)(-s * R.mx + c * R.my + P.cy - f.Y0 + tb * ddy);
-  g.pz = (float)((double)R.gz - f.Z0 + tb * (double)R.dz);
-  g.dx = (float)(P.step * ddx);
-  g.dy = (float)(P.step * ddy);
-  g.dz = (float)(P.step * (double)R.dz);
-  g.tb = (float)tb;
+__device__ inline SegPos seg_pos(const float4& pw, const float4& dn, int cnt, const Foot& f, float c, float s,
+                                 float sc, float ss, float step) {
+  SegPos g;
+  g.px = fmaf(c, pw.x, fmaf(s, pw.y, f.cx));
+  g.py = fmaf(c, pw.y, fmaf(-s, pw.x, f.cy));
+  g.pz = pw.z + f.zoff;
+  g.dx = fmaf(sc, dn.x, ss * dn.y);
+  g.dy = fmaf(sc, dn.y, -ss * dn.x);
+  g.dz = step * dn.z;
+  const int m = (cnt - 1) >> 1;
+  g.k0 = (float)(-m);
+  g.k1 = (float)(cnt - 1 - m);
   return g;
 }
 
-// CACHE keeps the 8 corner values of the current cell in registers: at
-// steps of half a voxel about a third of the samples stay in the cell of the
-// previous one and then read nothing from LDS.
-template <int B, bool CACHE>
-__global__ __launch_bounds__(256) void k_forward_boxc(MarchParams P, BoxParams Bp, const float* __restrict__ vol,
-                                                      float* __restrict__ part, int64_t n_rays, int smax) {
+// Lower bound of the unclamped fast path: a sample computed as
+// fma(k, d, p) lies within one rounding (< 2^-20 cell here) of the segment
+// between its endpoints, so endpoints at >= 2^-12 keep every sample's floor
+// >= 0.
+constexpr float kLo = 1.0f / 4096.0f;
+
+// True when every sample of the segment lies inside [kLo, h] on all axes, so
+// the sample loop needs no clamps (the samples lie on the line between its
+// two ends).
+__device__ inline bool seg_inside(const SegPos& g, float hx, float hy, float hz) {
+  const float x0 = fmaf(g.k0, g.dx, g.px), y0 = fmaf(g.k0, g.dy, g.py), z0 = fmaf(g.k0, g.dz, g.pz);
+  const float x1 = fmaf(g.k1, g.dx, g.px), y1 = fmaf(g.k1, g.dy, g.py), z1 = fmaf(g.k1, g.dz, g.pz);
+  return fminf(x0, x1) >= kLo && fmaxf(x0, x1) <= hx && fminf(y0, y1) >= kLo && fmaxf(y0, y1) <= hy &&
+         fminf(z0, z1) >= kLo && fmaxf(z0, z1) <= hz;
+}
+
+// Coordinate of a sample, clamped into [0, h] where the segment may leave
+// the footprint (rounding at its faces, or a box beyond the padded grid,
+// whose samples then read or write only padding).
+template <bool CLAMP>
+__device__ inline float coord(float k, float d, float p, float h) {
+  const float x = fmaf(k, d, p);
+  return CLAMP ? __builtin_amdgcn_fmed3f(x, 0.0f, h) : x;
+}
+
+// ------------------------------------------------------------- forward ---
+//
+// The workgroup of a (box, angle) stages the rotated box footprint of the
+// padded volume in LDS (one coalesced read per cell), then every segment of
+// the box gathers its samples from LDS.  The segment's partial sum (Horner
+// over its samples from the far end, S <- S r + val with r = exp(-alpha
+// step) applied as r_hi + r_lo, times the weight of its first sample) is
+// written to part[angle][rank][ray]; a second kernel adds, per pixel, the
+// partials of its rays in a fixed order (pupil index, then rank), so the
+// result does not depend on scheduling.
+
+template <int SY, int SZ, bool CLAMP>
+__device__ inline float march_forward(const float* sv, const SegPos& g, float hx, float hy, float hz,
+                                      float r_hi, float r_lo) {
+  float S = 0.0f;
+  for (float kf = g.k1; kf >= g.k0; kf -= 1.0f) {
+    const float x = coord<CLAMP>(kf, g.dx, g.px, hx);
+    const float y = coord<CLAMP>(kf, g.dy, g.py, hy);
+    const float z = coord<CLAMP>(kf, g.dz, g.pz, hz);
+    const float fx = __builtin_amdgcn_fractf(x), fy = __builtin_amdgcn_fractf(y), fz = __builtin_amdgcn_fractf(z);
+    const unsigned o = __umul24((unsigned)z, SZ) + __umul24((unsigned)y, SY) + (unsigned)x;
+    const float* p = sv + o;
+    const float* q = p + SZ;
+    const float v0 = p[0], v1 = p[1], v2 = p[SY], v3 = p[SY + 1];
+    const float v4 = q[0], v5 = q[1], v6 = q[SY], v7 = q[SY + 1];
+    const float c00 = fmaf(fx, v1 - v0, v0);
+    const float c01 = fmaf(fx, v3 - v2, v2);
+    const float c10 = fmaf(fx, v5 - v4, v4);
+    const float c11 = fmaf(fx, v7 - v6, v6);
+    const float c0 = fmaf(fy, c01 - c00, c00);
+    const float c1 = fmaf(fy, c11 - c10, c10);
+    const float val = fmaf(fz, c1 - c0, c0);
+    S = fmaf(S, r_hi, fmaf(S, r_lo, val));
+  }
+  return S;
+}
+
+template <int B>
+__global__ __launch_bounds__(256) void k_forward_box(MarchParams P, BoxParams Bp, const float* __restrict__ vol,
+                                                     float* __restrict__ part, int64_t slots) {
   constexpr int SY = Fixed<B>::WXY, SZ = SY * SY, NC = SZ * Fixed<B>::WZ;
   __shared__ float sv[NC];
   int b, a;
@@ -635,576 +653,55 @@ __global__ __launch_bounds__(256) void k_forward_boxc(MarchParams P, BoxParams B
   }
   __syncthreads();
   const float hx = (float)f.WX - 1.001f, hy = (float)f.WY - 1.001f, hz = (float)f.WZ - 1.001f;
+  const float c = (float)cs.x, s = (float)cs.y, sc = P.step * c, ss = P.step * s;
   const int s_end = Bp.box_begin[b + 1];
-  float* out = part + (int64_t)a * smax * n_rays;
+  float* out = part + (int64_t)a * slots;
   for (int si = Bp.box_begin[b] + threadIdx.x; si < s_end; si += blockDim.x) {
-    const int4 sg = Bp.segs[si];
-    const int r = sg.x, cnt = sg.z;
-    const RayRec R = P.rays[r];
-    const SegStart g = seg_start(P, R, cs.x, cs.y, f, sg.y);
-    float S = 0.0f;
-    float kf = (float)(cnt - 1);
-    unsigned cur = 0xffffffffu;
-    float v0 = 0.0f, v1 = 0.0f, v2 = 0.0f, v3 = 0.0f, v4 = 0.0f, v5 = 0.0f, v6 = 0.0f, v7 = 0.0f;
-    for (int k = cnt - 1; k >= 0; --k, kf -= 1.0f) {
-      const float x = __builtin_amdgcn_fmed3f(fmaf(kf, g.dx, g.px), 0.0f, hx);
-      const float y = __builtin_amdgcn_fmed3f(fmaf(kf, g.dy, g.py), 0.0f, hy);
-      const float z = __builtin_amdgcn_fmed3f(fmaf(kf, g.dz, g.pz), 0.0f, hz);
-      const float fx = __builtin_amdgcn_fractf(x), fy = __builtin_amdgcn_fractf(y),
-                  fz = __builtin_amdgcn_fractf(z);
-      const unsigned o = __umul24((unsigned)z, SZ) + __umul24((unsigned)y, SY) + (unsigned)x;
-      if (!CACHE || o != cur) {
-        const float* p = sv + o;
-        const float* q = p + SZ;
-        v0 = p[0];
-        v1 = p[1];
-        v2 = p[SY];
-        v3 = p[SY + 1];
-        v4 = q[0];
-        v5 = q[1];
-        v6 = q[SY];
-        v7 = q[SY + 1];
-        cur = o;
-      }
-      const float c00 = fmaf(fx, v1 - v0, v0);
-      const float c01 = fmaf(fx, v3 - v2, v2);
-      const float c10 = fmaf(fx, v5 - v4, v4);
-      const float c11 = fmaf(fx, v7 - v6, v6);
-      const float c0 = fmaf(fy, c01 - c00, c00);
-      const float c1 = fmaf(fy, c11 - c10, c10);
-      const float val = fmaf(fz, c1 - c0, c0);
-      S = fmaf(S, P.r_hi, fmaf(S, P.r_lo, val));
-    }
-    out[(int64_t)sg.w * n_rays + r] = R.cw * __builtin_amdgcn_exp2f(P.nb * g.tb) * S;
-  }
-}
-
-// LDS adds of the deposit: FP64, or 32-bit integers in fixed point (the
-// values already carry the workgroup's scale S and are rounded to the
-// nearest integer, halves upwards, by one v_cvt_rpi_i32_f32).
-__device__ inline int round_to_int(float v) {
-  int r;
-  asm("v_cvt_rpi_i32_f32 %0, %1" : "=v"(r) : "v"(v));
-  return r;
-}
-template <typename LT>
-__device__ inline void lds_add(LT* p, float v, float S);
-template <>
-__device__ inline void lds_add<double>(double* p, float v, float) {
-  atomicAdd(p, (double)v);
-}
-template <>
-__device__ inline void lds_add<int>(int* p, float v, float) {
-  atomicAdd(p, round_to_int(v));
-}
-// Packed pairs: the 64-bit word of a cell holds the exact integer
-// hi * 2^32 + lo, the sum of the fixed-point deposits into corner x (lo) and
-// corner x + 1 (hi) of the lanes whose cell it is.  Both parts stay within
-// +-2^31, so the sign-extended low half of the word is the x corner's sum
-// and the rest, shifted down by 32, the x + 1 corner's.
-__device__ inline unsigned long long pack_pair(float lo_v, float hi_v) {
-  const int lo = round_to_int(lo_v), hi = round_to_int(hi_v);
-  return ((unsigned long long)(unsigned)(hi + (lo >> 31)) << 32) | (unsigned)lo;
-}
-__device__ inline void lds_add_pair(long long* p, float lo, float hi) {
-  atomicAdd((unsigned long long*)p, pack_pair(lo, hi));
-}
-
-// LT = int: the footprint is accumulated in 32-bit fixed point (gfx950 adds
-// 32-bit integers in LDS about twice as fast as FP64).  Overflow is ruled
-// out per workgroup: a cell's sum is bounded by (samples inside one voxel's
-// support) x (largest sample weight), where the first factor is n_supp, the
-// most samples of all rays in any 4 x 4 x 3 block of lab-frame unit cells
-// (the turned support of a voxel fits in such a block), and the second is
-// step / n_pupil times the largest |projection value| among the box's
-// segments at this angle.  S is the power of two that maps that bound to at
-// most 2^30, so every partial sum stays below 2^31 and S is exact; the
-// rounding error of an add is at most 1/(2S).  A non-finite projection value
-// makes the whole footprint NaN.
-template <int B, typename PT, int AGG, int NT, typename LT>
-__global__ __launch_bounds__(NT) void k_back_boxc(MarchParams P, BoxParams Bp, const PT* __restrict__ proj,
-                                                  double* __restrict__ dose) {
-  // slice pitch one word longer than a slice: the 32-bit deposit at edge 12
-  // measured 3 % faster than with SY * SY (pitches SY * SY + 2 .. + 4 were
-  // slower again; the pitch decides which LDS banks the lanes' adds share);
-  // packed pairs keep SY * SY so that four workgroups fit in the LDS
-  constexpr int SY = Fixed<B>::WXY, SZ = SY * SY + (sizeof(LT) == 8 ? 0 : 1), NC = SZ * Fixed<B>::WZ;
-  constexpr bool kInt = std::is_integral<LT>::value;      // fixed point
-  constexpr bool kPair = kInt && sizeof(LT) == 8;          // packed x pairs
-  static_assert(!kPair || AGG == 1, "packed pairs are built with run aggregation only");
-  __shared__ LT acc[NC];
-  __shared__ unsigned s_pvmax;
-  __shared__ int s_bad;
-  int b, a;
-  if (!work_item(Bp.nboxes, Bp.na, Bp.xcd, b, a)) return;
-  const double2 cs = P.cs[P.a0 + a];
-  const Foot f = footprint(Bp, Bp.box_id[b], cs.x, cs.y, P.cx, P.cy);
-  for (int i = threadIdx.x; i < NC; i += blockDim.x) acc[i] = (LT)0;
-  if (kInt && threadIdx.x == 0) {
-    s_pvmax = 0u;
-    s_bad = 0;
-  }
-  __syncthreads();
-  const float hx = (float)f.WX - 1.001f, hy = (float)f.WY - 1.001f, hz = (float)f.WZ - 1.001f;
-  const int64_t pbase = (int64_t)a * Bp.npix;
-  const int s_end = Bp.box_begin[b + 1];
-  float S = 1.0f;
-  double invS = 1.0;
-  bool bad = false;
-  if (kInt) {
-    float m = 0.0f;
-    bool nonfinite = false;
-    for (int si = Bp.box_begin[b] + threadIdx.x; si < s_end; si += blockDim.x) {
-      const float apv = fabsf(load_p(proj, pbase + Bp.segs[si].x % Bp.npix));
-      if (apv <= 3.4028234e38f)
-        m = fmaxf(m, apv);
-      else
-        nonfinite = true;
-    }
-    atomicMax(&s_pvmax, __float_as_uint(m));  // non-negative floats order as their bits
-    if (nonfinite) atomicOr(&s_bad, 1);
-    __syncthreads();
-    bad = s_bad != 0;
-    const double bound = Bp.supp_coef * (double)__uint_as_float(s_pvmax);
-    int e2 = 0;
-    if (bound > 0.0) e2 = min(max((int)floor(log2(1073741824.0 / bound)), -120), 120);
-    S = ldexpf(1.0f, e2);
-    invS = ldexp(1.0, -e2);
-  }
-  for (int si = Bp.box_begin[b] + threadIdx.x; si < s_end; si += blockDim.x) {
-    const int4 sg = Bp.segs[si];
-    const int r = sg.x, cnt = sg.z;
-    const float pv = load_p(proj, pbase + r % Bp.npix);
-    if (pv == 0.0f) continue;
-    const RayRec R = P.rays[r];
-    const SegStart g = seg_start(P, R, cs.x, cs.y, f, sg.y);
-    float e = R.cw * pv * __builtin_amdgcn_exp2f(P.nb * g.tb);
-    if (kInt) e *= S;  // sample weights in the fixed-point units
-    float kf = 0.0f;
-    const float kend = (float)cnt;  // exact: a segment has fewer than 2^24 samples
-    float w[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    // AGG == 2: the cell whose corners w holds, starting at the first sample's
-    int cx = 0, cy = 0, cz = 0;
-    unsigned base = 0;
-    if (AGG == 2) {
-      cx = (int)__builtin_amdgcn_fmed3f(g.px, 0.0f, hx);
-      cy = (int)__builtin_amdgcn_fmed3f(g.py, 0.0f, hy);
-      cz = (int)__builtin_amdgcn_fmed3f(g.pz, 0.0f, hz);
-      base = __umul24((unsigned)cz, SZ) + __umul24((unsigned)cy, SY) + (unsigned)cx;
-    }
-    // AGG == 1: byte offset in acc of the cell whose corners w holds, also
-    // starting at the first sample's (w is zero until its first add)
-    constexpr unsigned kL = sizeof(LT);
-    auto cell_bytes = [&](float x, float y, float z) {
-      return __umul24((unsigned)z, SZ * kL) + __umul24((unsigned)y, SY * kL) + (unsigned)x * kL;
-    };
-    unsigned cur = 0;
-    if (AGG == 1)
-      cur = cell_bytes(__builtin_amdgcn_fmed3f(g.px, 0.0f, hx), __builtin_amdgcn_fmed3f(g.py, 0.0f, hy),
-                       __builtin_amdgcn_fmed3f(g.pz, 0.0f, hz));
-    for (; kf < kend; kf += 1.0f) {
-      const float x = __builtin_amdgcn_fmed3f(fmaf(kf, g.dx, g.px), 0.0f, hx);
-      const float y = __builtin_amdgcn_fmed3f(fmaf(kf, g.dy, g.py), 0.0f, hy);
-      const float z = __builtin_amdgcn_fmed3f(fmaf(kf, g.dz, g.pz), 0.0f, hz);
-      const float fx = __builtin_amdgcn_fractf(x), fy = __builtin_amdgcn_fractf(y),
-                  fz = __builtin_amdgcn_fractf(z);
-      const unsigned o = __umul24((unsigned)z, SZ) + __umul24((unsigned)y, SY) + (unsigned)x;
-      const float z1 = e * fz, z0 = e - z1;
-      const float y01 = z0 * fy, y00 = z0 - y01;
-      const float y11 = z1 * fy, y10 = z1 - y11;
-      const float q[8] = {y00 - y00 * fx, y00 * fx, y01 - y01 * fx, y01 * fx,
-                          y10 - y10 * fx, y10 * fx, y11 - y11 * fx, y11 * fx};
-      if constexpr (AGG == 2) {
-        // Corner sharing: moving one cell along an axis keeps the four
-        // corners on the far face, so only the four on the near face are
-        // added to LDS; the kept sums shift to the near side and the far
-        // side restarts at zero.  Steps of more than one cell (only possible
-        // for Delta s > 1) flush all eight corners.
-        const int ix = (int)x, iy = (int)y, iz = (int)z;
-        int ex = ix - cx, ey = iy - cy, ez = iz - cz;
-        if (P.step > 1.0f) {
-          if (ex < -1 || ex > 1 || ey < -1 || ey > 1 || ez < -1 || ez > 1) {
-            LT* p = acc + base;
-            lds_add(p, w[0], S);
-            lds_add(p + 1, w[1], S);
-            lds_add(p + SY, w[2], S);
-            lds_add(p + SY + 1, w[3], S);
-            lds_add(p + SZ, w[4], S);
-            lds_add(p + SZ + 1, w[5], S);
-            lds_add(p + SZ + SY, w[6], S);
-            lds_add(p + SZ + SY + 1, w[7], S);
-#pragma unroll
-            for (int c = 0; c < 8; ++c) w[c] = 0.0f;
-            cx = ix;
-            cy = iy;
-            cz = iz;
-            base = __umul24((unsigned)cz, SZ) + __umul24((unsigned)cy, SY) + (unsigned)cx;
-            ex = ey = ez = 0;
-          }
-        }
-        if (ex != 0) {
-          const bool up = ex > 0;  // near face: corners with x bit 0 (up) or 1
-          LT* p = acc + base + (up ? 0 : 1);
-          lds_add(p, (up ? w[0] : w[1]), S);
-          lds_add(p + SY, (up ? w[2] : w[3]), S);
-          lds_add(p + SZ, (up ? w[4] : w[5]), S);
-          lds_add(p + SZ + SY, (up ? w[6] : w[7]), S);
-#pragma unroll
-          for (int c = 0; c < 8; c += 2) {
-            const float lo = w[c], hi = w[c + 1];
-            w[c] = up ? hi : 0.0f;
-            w[c + 1] = up ? 0.0f : lo;
-          }
-          base += ex;
-          cx = ix;
-        }
-        if (ey != 0) {
-          const bool up = ey > 0;
-          LT* p = acc + base + (up ? 0 : SY);
-          lds_add(p, (up ? w[0] : w[2]), S);
-          lds_add(p + 1, (up ? w[1] : w[3]), S);
-          lds_add(p + SZ, (up ? w[4] : w[6]), S);
-          lds_add(p + SZ + 1, (up ? w[5] : w[7]), S);
-          const int pair[4] = {0, 1, 4, 5};
-#pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            const int c = pair[j];
-            const float lo = w[c], hi = w[c + 2];
-            w[c] = up ? hi : 0.0f;
-            w[c + 2] = up ? 0.0f : lo;
-          }
-          base += ey * SY;
-          cy = iy;
-        }
-        if (ez != 0) {
-          const bool up = ez > 0;
-          LT* p = acc + base + (up ? 0 : SZ);
-          lds_add(p, (up ? w[0] : w[4]), S);
-          lds_add(p + 1, (up ? w[1] : w[5]), S);
-          lds_add(p + SY, (up ? w[2] : w[6]), S);
-          lds_add(p + SY + 1, (up ? w[3] : w[7]), S);
-#pragma unroll
-          for (int c = 0; c < 4; ++c) {
-            const float lo = w[c], hi = w[c + 4];
-            w[c] = up ? hi : 0.0f;
-            w[c + 4] = up ? 0.0f : lo;
-          }
-          base += ez * SZ;
-          cz = iz;
-        }
-#pragma unroll
-        for (int c = 0; c < 8; ++c) w[c] += q[c];
-      } else if constexpr (AGG == 1) {
-        // The run's sums are only read inside the flush and restart through
-        // keep = 0, so the loop carries w and cur without copies between
-        // iterations.
-        const unsigned ob = cell_bytes(x, y, z);
-        const bool fl = ob != cur;
-        if (fl) {
-          LT* p = (LT*)((char*)acc + cur);
-          if constexpr (kPair) {
-            lds_add_pair(p, w[0], w[1]);
-            lds_add_pair(p + SY, w[2], w[3]);
-            lds_add_pair(p + SZ, w[4], w[5]);
-            lds_add_pair(p + SZ + SY, w[6], w[7]);
-          } else {
-            lds_add(p, w[0], S);
-            lds_add(p + 1, w[1], S);
-            lds_add(p + SY, w[2], S);
-            lds_add(p + SY + 1, w[3], S);
-            lds_add(p + SZ, w[4], S);
-            lds_add(p + SZ + 1, w[5], S);
-            lds_add(p + SZ + SY, w[6], S);
-            lds_add(p + SZ + SY + 1, w[7], S);
-          }
-        }
-        const float keep = fl ? 0.0f : 1.0f;
-        cur = ob;
-        // w[2j] += yz (1 - fx), w[2j+1] += yz fx, written so that every
-        // update accumulates into w itself
-        const float yz[4] = {y00, y01, y10, y11};
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          w[2 * j] = fmaf(-yz[j], fx, fmaf(keep, w[2 * j], yz[j]));
-          w[2 * j + 1] = fmaf(yz[j], fx, keep * w[2 * j + 1]);
-        }
-      } else {
-        LT* p = acc + o;
-        lds_add(p, q[0], S);
-        lds_add(p + 1, q[1], S);
-        lds_add(p + SY, q[2], S);
-        lds_add(p + SY + 1, q[3], S);
-        lds_add(p + SZ, q[4], S);
-        lds_add(p + SZ + 1, q[5], S);
-        lds_add(p + SZ + SY, q[6], S);
-        lds_add(p + SZ + SY + 1, q[7], S);
-      }
-      e = fmaf(e, P.r_hi, e * P.r_lo);
-    }
-    if constexpr (AGG == 2) {
-      if (cnt > 0) {
-        LT* p = acc + base;
-        lds_add(p, w[0], S);
-        lds_add(p + 1, w[1], S);
-        lds_add(p + SY, w[2], S);
-        lds_add(p + SY + 1, w[3], S);
-        lds_add(p + SZ, w[4], S);
-        lds_add(p + SZ + 1, w[5], S);
-        lds_add(p + SZ + SY, w[6], S);
-        lds_add(p + SZ + SY + 1, w[7], S);
-      }
-    } else if constexpr (kPair) {
-      if (cnt > 0) {
-        LT* p = (LT*)((char*)acc + cur);
-        lds_add_pair(p, w[0], w[1]);
-        lds_add_pair(p + SY, w[2], w[3]);
-        lds_add_pair(p + SZ, w[4], w[5]);
-        lds_add_pair(p + SZ + SY, w[6], w[7]);
-      }
-    } else if constexpr (AGG == 1) {
-      if (cnt > 0) {
-        LT* p = (LT*)((char*)acc + cur);
-        lds_add(p, w[0], S);
-        lds_add(p + 1, w[1], S);
-        lds_add(p + SY, w[2], S);
-        lds_add(p + SY + 1, w[3], S);
-        lds_add(p + SZ, w[4], S);
-        lds_add(p + SZ + 1, w[5], S);
-        lds_add(p + SZ + SY, w[6], S);
-        lds_add(p + SZ + SY + 1, w[7], S);
-      }
-    }
-  }
-  __syncthreads();
-  for (int i = threadIdx.x; i < NC; i += blockDim.x) {
-    LT raw = acc[i];
-    if (!kPair && raw == (LT)0 && !bad) continue;
-    const int z = i / SZ, rem = i - z * SZ, y = rem / SY, x = rem - y * SY;
-    if (x >= f.WX || y >= f.WY || z >= f.WZ) continue;
-    if constexpr (kPair) {
-      // this cell's sum: the low half of its own word plus the high half of
-      // the word of its x - 1 neighbour in the same row
-      const long long lo = (long long)(int)(unsigned)raw;
-      long long hi = 0;
-      if (x > 0) {
-        const long long u = acc[i - 1];
-        hi = (u - (long long)(int)(unsigned)u) >> 32;
-      }
-      raw = lo + hi;
-      if (raw == 0 && !bad) continue;
-    }
-    const int64_t gi = ((int64_t)(f.Z0 + z) * Bp.py + (f.Y0 + y)) * Bp.px + (f.X0 + x);
-    unsafeAtomicAdd(dose + gi, bad ? __builtin_nan("") : (double)raw * invS);
-  }
-}
-
-// Fixed-footprint kernels exist for these edges; other edges use the
-// runtime-stride kernels above.
-static bool fixed_edge(int B) { return B == 8 || B == 12 || B == 16; }
-
-BoxParams box_params(const vam_geometry* h) {
-  BoxParams Bp;
-  Bp.G = h->boxes;
-  Bp.nboxes = h->n_boxes;
-  Bp.na = 0;
-  Bp.xcd = 0;
-  Bp.segs = h->segs;
-  Bp.box_begin = h->box_begin;
-  Bp.box_id = h->box_id;
-  footprint_bound(h->boxes.B, h->px, h->py, h->pz, Bp.wxy_max, Bp.wz_max);
-  Bp.npix = h->desc.n_u * h->desc.n_v;
-  Bp.px = h->px;
-  Bp.py = h->py;
-  Bp.pz = h->pz;
-  Bp.supp_coef = (double)h->n_supp * h->desc.step / h->desc.n_pupil;
-  return Bp;
-}
-
-template <typename PT, typename LT, bool AGG>
-static void launch_box_k(vam_geometry* h, const MarchParams& P, const BoxParams& Bp, const PT* proj, int na,
-                         hipStream_t s) {
-  const size_t lds = (size_t)h->box_cells * sizeof(LT);
-  static thread_local int configured = 0;  // bit per (LT, AGG) instantiation
-  const int bit = (sizeof(LT) == 8 ? 1 : 0) + (AGG ? 2 : 0);
-  if (!(configured & (1 << bit))) {
-    (void)hipFuncSetAttribute((const void*)k_back_box<PT, LT, AGG>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              kMaxLdsBytes);
-    configured |= 1 << bit;
-  }
-  BoxParams Bw = Bp;
-  Bw.nboxes = h->n_boxes;
-  Bw.na = na;
-  Bw.xcd = h->xcd_deposit;
-  hipLaunchKernelGGL((k_back_box<PT, LT, AGG>), work_grid(h->n_boxes, na, Bw.xcd), dim3(256), lds, s, P, Bw, proj,
-                     h->dose_pad64);
-}
-
-template <int B, typename PT, int AGG, typename LT>
-static void launch_boxc(vam_geometry* h, const MarchParams& P, const BoxParams& Bp, const PT* proj, int na,
-                        hipStream_t s) {
-  BoxParams Bw = Bp;
-  Bw.nboxes = h->n_boxes;
-  Bw.na = na;
-  Bw.xcd = h->xcd_deposit;
-  const dim3 grid = work_grid(h->n_boxes, na, Bw.xcd);
-  if (h->deposit_threads == 512)
-    hipLaunchKernelGGL((k_back_boxc<B, PT, AGG, 512, LT>), grid, dim3(512), 0, s, P, Bw, proj, h->dose_pad64);
-  else
-    hipLaunchKernelGGL((k_back_boxc<B, PT, AGG, 256, LT>), grid, dim3(256), 0, s, P, Bw, proj, h->dose_pad64);
-}
-
-template <int B, typename PT, typename LT>
-static void launch_boxc_agg(vam_geometry* h, const MarchParams& P, const BoxParams& Bp, const PT* proj, int na,
-                            int agg, hipStream_t s) {
-  switch (agg) {
-    case 0: launch_boxc<B, PT, 0, LT>(h, P, Bp, proj, na, s); break;
-    case 1: launch_boxc<B, PT, 1, LT>(h, P, Bp, proj, na, s); break;
-    default: launch_boxc<B, PT, 2, LT>(h, P, Bp, proj, na, s); break;
-  }
-}
-
-template <typename PT, typename LT>
-static void launch_boxc_edge(vam_geometry* h, const MarchParams& P, const BoxParams& Bp, const PT* proj, int na,
-                             int agg, hipStream_t s) {
-  switch (h->boxes.B) {
-    case 8: launch_boxc_agg<8, PT, LT>(h, P, Bp, proj, na, agg, s); break;
-    case 12: launch_boxc_agg<12, PT, LT>(h, P, Bp, proj, na, agg, s); break;
-    default: launch_boxc_agg<16, PT, LT>(h, P, Bp, proj, na, agg, s); break;
+    const float4 pw = Bp.seg.pw[si], dn = Bp.seg.dn[si];
+    const SegPos g = seg_pos(pw, dn, __float_as_int(dn.w), f, c, s, sc, ss, P.step);
+    const float S = seg_inside(g, hx, hy, hz) ? march_forward<SY, SZ, false>(sv, g, hx, hy, hz, P.r_hi, P.r_lo)
+                                              : march_forward<SY, SZ, true>(sv, g, hx, hy, hz, P.r_hi, P.r_lo);
+    out[Bp.seg.idx[si]] = pw.w * S;
   }
 }
 
 template <typename PT>
-static void launch_boxc_pair(vam_geometry* h, const MarchParams& P, const BoxParams& Bp, const PT* proj, int na,
-                             hipStream_t s) {
-  switch (h->boxes.B) {
-    case 8: launch_boxc<8, PT, 1, long long>(h, P, Bp, proj, na, s); break;
-    case 12: launch_boxc<12, PT, 1, long long>(h, P, Bp, proj, na, s); break;
-    default: launch_boxc<16, PT, 1, long long>(h, P, Bp, proj, na, s); break;
+__device__ inline void store_proj(PT* p, int64_t i, float x);
+template <>
+__device__ inline void store_proj<float>(float* p, int64_t i, float x) {
+  p[i] = x;
+}
+template <>
+__device__ inline void store_proj<uint16_t>(uint16_t* p, int64_t i, float x) {
+  uint32_t u = __float_as_uint(x);
+  if ((u & 0x7fffffffu) > 0x7f800000u) {
+    p[i] = (uint16_t)((u >> 16) | 0x40u);  // quiet NaN
+  } else {
+    u += 0x7fffu + ((u >> 16) & 1u);       // round to nearest even
+    p[i] = (uint16_t)(u >> 16);
   }
 }
-
-// Deposit variants of the box kernels: 6, 8, 10 accumulate the footprint in
-// FP64, 13, 11, 12 in 32-bit fixed point, each without aggregation, with
-// cell-run aggregation and with corner sharing; 14 in fixed point packed in
-// 64-bit x pairs, with run aggregation.  Edges without a fixed-footprint
-// kernel use the runtime-stride FP64 kernels.
-template <typename PT>
-static void launch_box_t(vam_geometry* h, const MarchParams& P, const PT* proj, int na, int variant,
-                         hipStream_t s) {
-  const BoxParams Bp = box_params(h);
-  const bool fixed = fixed_edge(h->boxes.B) && h->fixed_kernels;
-  const int agg = (variant == 10 || variant == 12) ? 2 : (variant == 8 || variant == 11 || variant == 14) ? 1 : 0;
-  if (fixed && variant == 14) {
-    launch_boxc_pair<PT>(h, P, Bp, proj, na, s);
-    return;
-  }
-  if (fixed && (variant == 6 || variant == 8 || variant == 10)) {
-    launch_boxc_edge<PT, double>(h, P, Bp, proj, na, agg, s);
-    return;
-  }
-  if (fixed && variant >= 11) {
-    launch_boxc_edge<PT, int>(h, P, Bp, proj, na, agg, s);
-    return;
-  }
-  if (variant >= 10) variant = agg ? 8 : 6;
-  switch (variant) {
-    case 7: launch_box_k<PT, float, false>(h, P, Bp, proj, na, s); break;
-    case 8: launch_box_k<PT, double, true>(h, P, Bp, proj, na, s); break;
-    default: launch_box_k<PT, double, false>(h, P, Bp, proj, na, s); break;
-  }
-}
-
-void launch_box_deposit(vam_geometry* h, const MarchParams& P, const void* proj, vam_dtype proj_t, int na,
-                        int variant, hipStream_t s) {
-  if (h->n_boxes == 0) return;
-  switch (proj_t) {
-    case VAM_F32: launch_box_t(h, P, (const float*)proj, na, variant, s); break;
-    case VAM_BF16: launch_box_t(h, P, (const uint16_t*)proj, na, variant, s); break;
-    case VAM_F16: launch_box_t(h, P, (const __half*)proj, na, variant, s); break;
-  }
-}
-
-
-// --------------------------------------------------------------- forward --
-//
-// Forward projection over the same decomposition: the workgroup of a
-// (box, angle) stages the rotated box footprint of the padded volume in LDS
-// (one coalesced read per cell), then every segment of the box gathers its
-// samples from LDS.  The segment's partial sum (Horner over its samples,
-// times the ray weight and the attenuation of its first sample) is written to
-// part[angle][rank][ray]; a second kernel adds, per pixel, the partials of
-// its rays in a fixed order (pupil index, then rank), so the result does not
-// depend on scheduling.
-
-template <typename AT>
-__global__ __launch_bounds__(256) void k_forward_box(MarchParams P, BoxParams Bp, const float* __restrict__ vol,
-                                                     float* __restrict__ part, int64_t n_rays, int smax) {
-  extern __shared__ float sv[];
-  int b, a;
-  if (!work_item(Bp.nboxes, Bp.na, Bp.xcd, b, a)) return;
-  const int box = Bp.box_id[b];
-  const double2 cs = P.cs[P.a0 + a];
-  const Foot f = footprint(Bp, box, cs.x, cs.y, P.cx, P.cy);
-  const int plane = f.WX * f.WY;
-  const int ncell = plane * f.WZ;
-  for (int i = threadIdx.x; i < ncell; i += blockDim.x) {
-    const int z = i / plane, rem = i - z * plane, y = rem / f.WX, x = rem - y * f.WX;
-    sv[i] = vol[((int64_t)(f.Z0 + z) * Bp.py + (f.Y0 + y)) * Bp.px + (f.X0 + x)];
-  }
-  __syncthreads();
-  const float lox = (float)f.X0, hix = (float)(f.X0 + f.WX) - 1.001f;
-  const float loy = (float)f.Y0, hiy = (float)(f.Y0 + f.WY) - 1.001f;
-  const float loz = (float)f.Z0, hiz = (float)(f.Z0 + f.WZ) - 1.001f;
-  const int sy = f.WX, sz = plane;
-  const int s_end = Bp.box_begin[b + 1];
-  float* out = part + (int64_t)a * smax * n_rays;
-  for (int si = Bp.box_begin[b] + threadIdx.x; si < s_end; si += blockDim.x) {
-    const int4 sg = Bp.segs[si];
-    const int r = sg.x, kb = sg.y, cnt = sg.z;
-    const RayRec R = P.rays[r];
-    const float gx = (float)(cs.x * R.mx + cs.y * R.my + P.cx);
-    const float gy = (float)(-cs.y * R.mx + cs.x * R.my + P.cy);
-    const float dx = (float)(cs.x * R.dx + cs.y * R.dy);
-    const float dy = (float)(-cs.y * R.dx + cs.x * R.dy);
-    const float tb = fmaf((float)(kb - R.k0), P.step, R.t0);
-    float S = 0.0f;
-    float kf = (float)(cnt - 1);
-    for (int k = cnt - 1; k >= 0; --k, kf -= 1.0f) {
-      const float t = fmaf(kf, P.step, tb);
-      const float x = __builtin_amdgcn_fmed3f(fmaf(t, dx, gx), lox, hix);
-      const float y = __builtin_amdgcn_fmed3f(fmaf(t, dy, gy), loy, hiy);
-      const float z = __builtin_amdgcn_fmed3f(fmaf(t, R.dz, R.gz), loz, hiz);
-      const float fx = __builtin_amdgcn_fractf(x), fy = __builtin_amdgcn_fractf(y),
-                  fz = __builtin_amdgcn_fractf(z);
-      const float* p = sv + (((int)z - f.Z0) * sz + ((int)y - f.Y0) * sy + ((int)x - f.X0));
-      const float c00 = fmaf(fx, p[1] - p[0], p[0]);
-      const float c01 = fmaf(fx, p[sy + 1] - p[sy], p[sy]);
-      const float c10 = fmaf(fx, p[sz + 1] - p[sz], p[sz]);
-      const float c11 = fmaf(fx, p[sz + sy + 1] - p[sz + sy], p[sz + sy]);
-      const float c0 = fmaf(fy, c01 - c00, c00);
-      const float c1 = fmaf(fy, c11 - c10, c10);
-      const float val = fmaf(fz, c1 - c0, c0);
-      S = fmaf(S, P.r_hi, fmaf(S, P.r_lo, val));
-    }
-    out[(int64_t)sg.w * n_rays + r] = R.cw * __builtin_amdgcn_exp2f(P.nb * tb) * S;
-  }
+template <>
+__device__ inline void store_proj<__half>(__half* p, int64_t i, float x) {
+  p[i] = __float2half_rn(x);
 }
 
 template <typename PT>
 __global__ void k_reduce_segments(const float* __restrict__ part, const int* __restrict__ nseg,
-                                  PT* __restrict__ proj, int npix, int np, int64_t n_rays, int smax, int na) {
+                                  PT* __restrict__ proj, int npix, int np, int64_t n_rays, int64_t slots,
+                                  int na) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= (int64_t)na * npix) return;
   const int a = (int)(i / npix);
   const int pix = (int)(i - (int64_t)a * npix);
-  const float* base = part + (int64_t)a * smax * n_rays;
+  const float* base = part + (int64_t)a * slots;
   float acc = 0.0f;
   for (int j = 0; j < np; ++j) {
     const int64_t r = (int64_t)j * npix + pix;
     const int ns = nseg[r];
     const float* b = base + r;
-    // four running sums in a fixed interleave keep four loads in flight
-    // (38 % faster than one chain); the order is the same on every call
+    // four running sums in a fixed interleave keep four loads in flight;
+    // the order is the same on every call
     float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f, s3 = 0.0f;
     int q = 0;
     for (; q + 4 <= ns; q += 4) {
@@ -1219,19 +716,23 @@ __global__ void k_reduce_segments(const float* __restrict__ part, const int* __r
   store_proj(proj, i, acc);
 }
 
+template <int B>
+static void launch_forward_box(dim3 grid, hipStream_t s, const MarchParams& P, const BoxParams& Bp,
+                               const float* vol, float* part, int64_t slots) {
+  hipLaunchKernelGGL((k_forward_box<B>), grid, dim3(256), 0, s, P, Bp, vol, part, slots);
+}
+
 template <typename PT>
 static vam_status forward_box_t(vam_geometry* h, const MarchParams& P0, PT* proj, int na, hipStream_t s) {
   const vam_geometry_desc& D = h->desc;
-  const int smax = std::max(h->max_seg_per_ray, 1);
-  const int64_t per_angle = (int64_t)smax * h->n_rays;
+  const int64_t slots = (int64_t)std::max(h->max_seg_per_ray, 1) * h->n_rays;
   if (!h->seg_part) {
-    // partial sums for a chunk of angles, at most ~8 GiB (5 chunks of 80
-    // angles at 256^3 with 16 pupil samples: 1.7 % faster than 2 GiB chunks,
-    // fewer launch tails and reductions); if the device cannot hold that
+    // partial sums for a chunk of angles, at most 8 GiB (fewer launch tails
+    // and reductions than small chunks); if the device cannot hold that
     // much, halve the chunk until the allocation succeeds
-    int64_t angles = std::max<int64_t>(1, std::min<int64_t>(D.n_angles, (int64_t(1) << 31) / per_angle));
+    int64_t angles = std::max<int64_t>(1, std::min<int64_t>(D.n_angles, (int64_t(1) << 31) / slots));
     for (;;) {
-      const hipError_t e = hipMalloc(&h->seg_part, per_angle * angles * sizeof(float));
+      const hipError_t e = dev_alloc((void**)&h->seg_part, slots * angles * sizeof(float));
       if (e == hipSuccess) break;
       h->seg_part = nullptr;
       if (e != hipErrorOutOfMemory || angles == 1) return hip_check(e, "allocating segment partial sums");
@@ -1240,41 +741,23 @@ static vam_status forward_box_t(vam_geometry* h, const MarchParams& P0, PT* proj
     }
     h->seg_part_angles = (int)angles;
   }
-  const BoxParams Bp = box_params(h);
-  const size_t lds = (size_t)h->box_cells * sizeof(float);
   const int npix = D.n_u * D.n_v;
   for (int c0 = 0; c0 < na; c0 += h->seg_part_angles) {
     const int nc = std::min(h->seg_part_angles, na - c0);
     MarchParams P = P0;
     P.a0 = P0.a0 + c0;
-    BoxParams Bw = Bp;
-    Bw.nboxes = h->n_boxes;
-    Bw.na = nc;
-    Bw.xcd = h->xcd_forward;
-    Bw.segs = h->segs_fwd;
-    if (h->n_boxes > 0 && fixed_edge(h->boxes.B) && h->fixed_kernels) {
-      const dim3 grid = work_grid(h->n_boxes, nc, Bw.xcd);
-      switch (h->boxes.B * 2 + (h->fwd_cache ? 1 : 0)) {
-        case 16: hipLaunchKernelGGL((k_forward_boxc<8, false>), grid, dim3(256), 0, s, P, Bw, h->vol_pad, h->seg_part, h->n_rays, smax); break;
-        case 17: hipLaunchKernelGGL((k_forward_boxc<8, true>), grid, dim3(256), 0, s, P, Bw, h->vol_pad, h->seg_part, h->n_rays, smax); break;
-        case 24: hipLaunchKernelGGL((k_forward_boxc<12, false>), grid, dim3(256), 0, s, P, Bw, h->vol_pad, h->seg_part, h->n_rays, smax); break;
-        case 25: hipLaunchKernelGGL((k_forward_boxc<12, true>), grid, dim3(256), 0, s, P, Bw, h->vol_pad, h->seg_part, h->n_rays, smax); break;
-        case 32: hipLaunchKernelGGL((k_forward_boxc<16, false>), grid, dim3(256), 0, s, P, Bw, h->vol_pad, h->seg_part, h->n_rays, smax); break;
-        default: hipLaunchKernelGGL((k_forward_boxc<16, true>), grid, dim3(256), 0, s, P, Bw, h->vol_pad, h->seg_part, h->n_rays, smax); break;
+    if (h->n_boxes > 0) {
+      const BoxParams Bp = box_params(h, h->seg_fwd, nc, h->xcd_forward);
+      const dim3 grid = work_grid(h->n_boxes, nc, Bp.xcd);
+      switch (h->boxes.B) {
+        case 8: launch_forward_box<8>(grid, s, P, Bp, h->vol_pad, h->seg_part, slots); break;
+        case 12: launch_forward_box<12>(grid, s, P, Bp, h->vol_pad, h->seg_part, slots); break;
+        default: launch_forward_box<16>(grid, s, P, Bp, h->vol_pad, h->seg_part, slots); break;
       }
-    } else if (h->n_boxes > 0) {
-      static thread_local bool configured = false;
-      if (!configured) {
-        (void)hipFuncSetAttribute((const void*)k_forward_box<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  kMaxLdsBytes);
-        configured = true;
-      }
-      hipLaunchKernelGGL((k_forward_box<float>), work_grid(h->n_boxes, nc, Bw.xcd), dim3(256), lds, s, P, Bw, h->vol_pad,
-                         h->seg_part, h->n_rays, smax);
     }
     const int64_t n = (int64_t)nc * npix;
     hipLaunchKernelGGL(k_reduce_segments<PT>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, h->seg_part,
-                       h->ray_nseg, proj + (int64_t)c0 * npix, npix, D.n_pupil, h->n_rays, smax, nc);
+                       h->ray_nseg, proj + (int64_t)c0 * npix, npix, D.n_pupil, h->n_rays, slots, nc);
     VAM_HIP_TRY(hipGetLastError(), "launching the box-tiled forward projector");
   }
   return VAM_OK;
@@ -1282,12 +765,208 @@ static vam_status forward_box_t(vam_geometry* h, const MarchParams& P0, PT* proj
 
 vam_status launch_box_forward(vam_geometry* h, const MarchParams& P, void* proj, vam_dtype proj_t, int na,
                               hipStream_t s) {
+  if (!h->boxes_ready)
+    return fail(VAM_ERR_INVALID_ARG, "the box decomposition is not available (a rebuild failed); "
+                                     "set the box edge again or create a new geometry");
   switch (proj_t) {
     case VAM_F32: return forward_box_t(h, P, (float*)proj, na, s);
     case VAM_BF16: return forward_box_t(h, P, (uint16_t*)proj, na, s);
     case VAM_F16: return forward_box_t(h, P, (__half*)proj, na, s);
   }
   return fail(VAM_ERR_INVALID_ARG, "unknown projection dtype");
+}
+
+// ------------------------------------------------------------- deposit ---
+//
+// The deposit adds 8 corner weights per sample into the (box, angle)
+// workgroup's LDS footprint in 32-bit fixed point (gfx950 adds 32-bit
+// integers in LDS ~45x faster than FP32 and ~2x faster than FP64), then adds
+// each touched cell to the padded FP64 accumulator once.  Overflow is ruled
+// out per workgroup: a cell's exact sum is at most bound = n x (step /
+// n_pupil) x M, where n is the box's n_supp (the most samples of the box in
+// any 4 x 4 x 3 block of lab-frame unit cells, which holds the turned
+// support of any voxel), no sample weight exceeds step / n_pupil times |P|,
+// and M is the largest |projection value| among the box's segments at this
+// angle.  With S = (2^31 - n - 2^12)(1 - 2^-12) / bound, each of the at most
+// n adds into a cell rounds a value that is within 2^-12 of exact (the FP32
+// run sums of at most a few thousand same-sign terms) to the nearest
+// integer, so every partial sum stays below 2^31 in magnitude; the rounding
+// error of an add is at most 1/(2S) ~ bound 2^-32.  A non-finite
+// projection value makes the whole footprint NaN.
+//
+// Run aggregation keeps the 8 corner sums of consecutive samples in one cell
+// in registers and adds them to LDS when the cell changes; the sums restart
+// through a factor keep in {0, 1} (w <- keep w + q, one FMA) rather than a
+// branch, so the loop carries them without register copies.
+
+template <typename PT>
+__device__ inline float load_p(const PT* p, int64_t i);
+template <>
+__device__ inline float load_p<float>(const float* p, int64_t i) {
+  return p[i];
+}
+template <>
+__device__ inline float load_p<uint16_t>(const uint16_t* p, int64_t i) {
+  return __uint_as_float((uint32_t)p[i] << 16);
+}
+template <>
+__device__ inline float load_p<__half>(const __half* p, int64_t i) {
+  return __half2float(p[i]);
+}
+
+// Round to the nearest integer, halves upwards (one v_cvt_rpi_i32_f32).
+__device__ inline int round_to_int(float v) {
+  int r;
+  asm("v_cvt_rpi_i32_f32 %0, %1" : "=v"(r) : "v"(v));
+  return r;
+}
+
+template <int SY, int SZ>
+__device__ inline void flush8(int* acc, unsigned cur, const float* w) {
+  int* p = (int*)((char*)acc + cur);
+  atomicAdd(p, round_to_int(w[0]));
+  atomicAdd(p + 1, round_to_int(w[1]));
+  atomicAdd(p + SY, round_to_int(w[2]));
+  atomicAdd(p + SY + 1, round_to_int(w[3]));
+  atomicAdd(p + SZ, round_to_int(w[4]));
+  atomicAdd(p + SZ + 1, round_to_int(w[5]));
+  atomicAdd(p + SZ + SY, round_to_int(w[6]));
+  atomicAdd(p + SZ + SY + 1, round_to_int(w[7]));
+}
+
+template <int SY, int SZ, bool CLAMP>
+__device__ inline void march_deposit(int* acc, const SegPos& g, float e, float hx, float hy, float hz,
+                                     float r_hi, float r_lo) {
+  auto cell_bytes = [](float x, float y, float z) {
+    return __umul24((unsigned)z, SZ * 4) + __umul24((unsigned)y, SY * 4) + (unsigned)x * 4;
+  };
+  float w[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  // byte offset of the cell whose corners w holds, starting at the first
+  // sample's (w is zero until its first add)
+  unsigned cur = cell_bytes(coord<CLAMP>(g.k0, g.dx, g.px, hx), coord<CLAMP>(g.k0, g.dy, g.py, hy),
+                            coord<CLAMP>(g.k0, g.dz, g.pz, hz));
+  // exact: a segment has fewer than 2^24 samples
+  for (float kf = g.k0; kf <= g.k1; kf += 1.0f) {
+    const float x = coord<CLAMP>(kf, g.dx, g.px, hx);
+    const float y = coord<CLAMP>(kf, g.dy, g.py, hy);
+    const float z = coord<CLAMP>(kf, g.dz, g.pz, hz);
+    const float fx = __builtin_amdgcn_fractf(x), fy = __builtin_amdgcn_fractf(y), fz = __builtin_amdgcn_fractf(z);
+    const float z1 = e * fz, z0 = e - z1;
+    const float y01 = z0 * fy, y00 = z0 - y01;
+    const float y11 = z1 * fy, y10 = z1 - y11;
+    const unsigned ob = cell_bytes(x, y, z);
+    const bool fl = ob != cur;
+    if (fl) flush8<SY, SZ>(acc, cur, w);
+    const float keep = fl ? 0.0f : 1.0f;
+    cur = ob;
+    // w[2j] += yz (1 - fx), w[2j+1] += yz fx, accumulated into w itself
+    const float yz[4] = {y00, y01, y10, y11};
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      w[2 * j] = fmaf(-yz[j], fx, fmaf(keep, w[2 * j], yz[j]));
+      w[2 * j + 1] = fmaf(yz[j], fx, keep * w[2 * j + 1]);
+    }
+    e = fmaf(e, r_hi, e * r_lo);
+  }
+  flush8<SY, SZ>(acc, cur, w);  // a segment has at least one sample
+}
+
+template <int B, typename PT, int NT>
+__global__ __launch_bounds__(NT) void k_back_box(MarchParams P, BoxParams Bp, const PT* __restrict__ proj,
+                                                 double* __restrict__ dose) {
+  // slice pitch one word longer than a slice: 3 % faster than SY * SY at
+  // edge 12 (the pitch decides which LDS banks the lanes' adds share)
+  constexpr int SY = Fixed<B>::WXY, SZ = SY * SY + 1, NC = SZ * Fixed<B>::WZ;
+  __shared__ int acc[NC];
+  __shared__ unsigned s_pvmax;
+  __shared__ int s_bad;
+  int b, a;
+  if (!work_item(Bp.nboxes, Bp.na, Bp.xcd, b, a)) return;
+  const double2 cs = P.cs[P.a0 + a];
+  const Foot f = footprint(Bp, Bp.box_id[b], cs.x, cs.y, P.cx, P.cy);
+  for (int i = threadIdx.x; i < NC; i += blockDim.x) acc[i] = 0;
+  if (threadIdx.x == 0) {
+    s_pvmax = 0u;
+    s_bad = 0;
+  }
+  __syncthreads();
+  const float hx = (float)f.WX - 1.001f, hy = (float)f.WY - 1.001f, hz = (float)f.WZ - 1.001f;
+  const int64_t pbase = (int64_t)a * Bp.npix;
+  const int s_end = Bp.box_begin[b + 1];
+  // the box's largest |projection value| at this angle sets the scale
+  float m = 0.0f;
+  bool nonfinite = false;
+  for (int si = Bp.box_begin[b] + threadIdx.x; si < s_end; si += blockDim.x) {
+    const float apv = fabsf(load_p(proj, pbase + Bp.seg.idx[si]));
+    if (apv <= 3.4028234e38f)
+      m = fmaxf(m, apv);
+    else
+      nonfinite = true;
+  }
+  atomicMax(&s_pvmax, __float_as_uint(m));  // non-negative floats order as their bits
+  if (nonfinite) atomicOr(&s_bad, 1);
+  __syncthreads();
+  const bool bad = s_bad != 0;
+  const int nb = Bp.box_supp[b];
+  const double bound = (double)nb * Bp.w_coef * (double)__uint_as_float(s_pvmax);
+  // capped below FP32's largest value (a smaller S only rounds coarser)
+  const float S = bound > 0.0 ? (float)fmin((2147483648.0 - nb - 4096.0) * (1.0 - 1.0 / 4096.0) / bound, 3.0e38)
+                              : 1.0f;
+  const double invS = 1.0 / (double)S;
+  const float c = (float)cs.x, s = (float)cs.y, sc = P.step * c, ss = P.step * s;
+  for (int si = Bp.box_begin[b] + threadIdx.x; si < s_end; si += blockDim.x) {
+    const float pv = load_p(proj, pbase + Bp.seg.idx[si]);
+    if (pv == 0.0f) continue;
+    const float4 pw = Bp.seg.pw[si], dn = Bp.seg.dn[si];
+    const SegPos g = seg_pos(pw, dn, __float_as_int(dn.w), f, c, s, sc, ss, P.step);
+    const float e = pw.w * pv * S;  // sample weights in the fixed-point units
+    if (seg_inside(g, hx, hy, hz))
+      march_deposit<SY, SZ, false>(acc, g, e, hx, hy, hz, P.r_hi, P.r_lo);
+    else
+      march_deposit<SY, SZ, true>(acc, g, e, hx, hy, hz, P.r_hi, P.r_lo);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < NC; i += blockDim.x) {
+    const int raw = acc[i];
+    if (raw == 0 && !bad) continue;
+    const int z = i / SZ, rem = i - z * SZ, y = rem / SY, x = rem - y * SY;
+    if (x >= f.WX || y >= f.WY || z >= f.WZ) continue;
+    const int64_t gi = ((int64_t)(f.Z0 + z) * Bp.py + (f.Y0 + y)) * Bp.px + (f.X0 + x);
+    unsafeAtomicAdd(dose + gi, bad ? __builtin_nan("") : (double)raw * invS);
+  }
+}
+
+template <int B, typename PT>
+static void launch_back_box(vam_geometry* h, const MarchParams& P, const PT* proj, int na, hipStream_t s) {
+  const BoxParams Bp = box_params(h, h->seg_dep, na, h->xcd_deposit);
+  const dim3 grid = work_grid(h->n_boxes, na, Bp.xcd);
+  if (h->deposit_threads == 512)
+    hipLaunchKernelGGL((k_back_box<B, PT, 512>), grid, dim3(512), 0, s, P, Bp, proj, h->dose_pad64);
+  else
+    hipLaunchKernelGGL((k_back_box<B, PT, 256>), grid, dim3(256), 0, s, P, Bp, proj, h->dose_pad64);
+}
+
+template <typename PT>
+static void launch_back_box_t(vam_geometry* h, const MarchParams& P, const PT* proj, int na, hipStream_t s) {
+  switch (h->boxes.B) {
+    case 8: launch_back_box<8, PT>(h, P, proj, na, s); break;
+    case 12: launch_back_box<12, PT>(h, P, proj, na, s); break;
+    default: launch_back_box<16, PT>(h, P, proj, na, s); break;
+  }
+}
+
+vam_status launch_box_deposit(vam_geometry* h, const MarchParams& P, const void* proj, vam_dtype proj_t, int na,
+                              hipStream_t s) {
+  if (!h->boxes_ready)
+    return fail(VAM_ERR_INVALID_ARG, "the box decomposition is not available (a rebuild failed); "
+                                     "set the box edge again or create a new geometry");
+  if (h->n_boxes == 0) return VAM_OK;
+  switch (proj_t) {
+    case VAM_F32: launch_back_box_t(h, P, (const float*)proj, na, s); break;
+    case VAM_BF16: launch_back_box_t(h, P, (const uint16_t*)proj, na, s); break;
+    case VAM_F16: launch_back_box_t(h, P, (const __half*)proj, na, s); break;
+  }
+  return VAM_OK;
 }
 
 }  // namespace vam

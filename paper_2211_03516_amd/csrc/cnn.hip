@@ -597,6 +597,35 @@ vam_status vam_cnn_get_params(vam_cnn_t h, float* params) {
   return VAM_OK;
 }
 
+vam_status vam_cnn_get_state(vam_cnn_t h, float* state, int64_t* adam_steps) {
+  clear_error();
+  if (!valid(h)) return fail(VAM_ERR_BAD_HANDLE, "not a live CNN handle");
+  if (!state || !adam_steps) return fail(VAM_ERR_INVALID_ARG, "NULL argument");
+  VAM_HIP_TRY(hipSetDevice(h->device), "hipSetDevice");
+  VAM_HIP_TRY(hipDeviceSynchronize(), "synchronising");
+  VAM_HIP_TRY(hipMemcpy(state, h->master, h->nparam * 4, hipMemcpyDeviceToHost), "copying parameters");
+  VAM_HIP_TRY(hipMemcpy(state + h->nparam, h->m1, h->nparam * 4, hipMemcpyDeviceToHost), "copying moments");
+  VAM_HIP_TRY(hipMemcpy(state + 2 * h->nparam, h->m2, h->nparam * 4, hipMemcpyDeviceToHost), "copying moments");
+  *adam_steps = h->adam_t;
+  return VAM_OK;
+}
+
+vam_status vam_cnn_set_state(vam_cnn_t h, const float* state, int64_t adam_steps) {
+  clear_error();
+  if (!valid(h)) return fail(VAM_ERR_BAD_HANDLE, "not a live CNN handle");
+  if (!state) return fail(VAM_ERR_INVALID_ARG, "NULL state");
+  if (adam_steps < 0 || adam_steps > (int64_t)1 << 40) return fail(VAM_ERR_INVALID_ARG, "bad Adam step count");
+  VAM_HIP_TRY(hipSetDevice(h->device), "hipSetDevice");
+  VAM_HIP_TRY(hipDeviceSynchronize(), "synchronising");
+  VAM_HIP_TRY(hipMemcpy(h->master, state, h->nparam * 4, hipMemcpyHostToDevice), "copying parameters");
+  VAM_HIP_TRY(hipMemcpy(h->m1, state + h->nparam, h->nparam * 4, hipMemcpyHostToDevice), "copying moments");
+  VAM_HIP_TRY(hipMemcpy(h->m2, state + 2 * h->nparam, h->nparam * 4, hipMemcpyHostToDevice), "copying moments");
+  h->adam_t = (int)adam_steps;
+  CNN_TRY(pack_all(h, nullptr));
+  VAM_HIP_TRY(hipDeviceSynchronize(), "packing weights");
+  return VAM_OK;
+}
+
 vam_status vam_cnn_get_grads(vam_cnn_t h, float* grads) {
   clear_error();
   if (!valid(h)) return fail(VAM_ERR_BAD_HANDLE, "not a live CNN handle");

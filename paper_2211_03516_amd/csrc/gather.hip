@@ -156,8 +156,8 @@ static vam_status build_gather(vam_geometry* h, hipStream_t s) {
   };
   const int threads = 256;
   const unsigned rblocks = (unsigned)((h->n_rays + threads - 1) / threads);
-  hipError_t e = hipMalloc(&count, ncell * sizeof(int));
-  if (e == hipSuccess) e = hipMalloc(&h->cell_begin, (ncell + 1) * sizeof(int));
+  hipError_t e = dev_alloc((void**)&count, ncell * sizeof(int));
+  if (e == hipSuccess) e = dev_alloc((void**)&h->cell_begin, (ncell + 1) * sizeof(int));
   if (e == hipSuccess) e = hipMemsetAsync(count, 0, ncell * sizeof(int), s);
   if (e != hipSuccess) {
     release();
@@ -186,8 +186,8 @@ static vam_status build_gather(vam_geometry* h, hipStream_t s) {
     free_gather(h);
     return fail(VAM_ERR_UNSUPPORTED, "gather deposit: more than 2^31 inverse-map entries");
   }
-  e = hipMalloc(&ent, std::max<int64_t>(total, 1) * sizeof(int4));
-  if (e == hipSuccess) e = hipMalloc(&h->gseg, std::max<int64_t>(total, 1) * 2 * sizeof(float4));
+  e = dev_alloc((void**)&ent, std::max<int64_t>(total, 1) * sizeof(int4));
+  if (e == hipSuccess) e = dev_alloc((void**)&h->gseg, std::max<int64_t>(total, 1) * 2 * sizeof(float4));
   if (e == hipSuccess)
     e = hipMemcpyAsync(h->cell_begin, hb.data(), (ncell + 1) * sizeof(int), hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipMemsetAsync(count, 0, ncell * sizeof(int), s);

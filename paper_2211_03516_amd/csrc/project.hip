@@ -1,24 +1,22 @@
-// The projector pair on gfx950: forward projection (Sec. 2.4 of Webber et
-// al., with the transmission factors of Sec. 2.5) and its exact transpose,
-// the dose deposit (Sec. 2.5).
+// Ray-driven reference kernels of the projector pair on gfx950: forward
+// projection (Sec. 2.4 of Webber et al., with the transmission factors of
+// Sec. 2.5) and its exact transpose, the dose deposit (Sec. 2.5), with one
+// lane per DMD pixel and angle; and the dispatch of both operators to the
+// box-tiled default kernels (boxes.hip), these references, or the
+// voxel-driven gather deposit (gather.hip).
 //
-// Work decomposition.  One lane per DMD pixel and angle; the lane marches
-// the n_pupil rays of its pixel one after the other (finite etendue,
-// Sec. 2.4/2.5) and sums them in registers, so the pupil reduction needs no
-// cross-lane traffic and a wave writes 64 consecutive projection values of
+// Work decomposition of the references.  The lane marches the n_pupil rays
+// of its pixel one after the other (finite etendue, Sec. 2.4/2.5) and sums
+// them in registers, so a wave writes 64 consecutive projection values of
 // one row (coalesced).  Lanes of a wave are 64 neighbouring pixels of one
-// row: at a given step their samples sit side by side in the volume, which
-// keeps the gathers of a wave within a few cache lines.
+// row: at a given step their samples sit side by side in the volume.
 //
 // Sampling.  The ray table keeps each resin segment as its midpoint and
 // direction (lab frame).  Per angle the midpoint and direction are rotated
 // into the volume frame in FP64 and rounded once; sample k is then at
 // g = m + t_k d with t_k = (k + 1/2 - K/2) step, one FMA per axis, short
-// lever arms and no accumulated drift.  The attenuation factor is
-// exp2(-alpha log2(e) t_k) times a per-ray constant that carries
-// exp(-alpha K step / 2), so every sample costs one exp2.  Anti-aliasing
-// weights (Sec. 2.2) are the trilinear tent over the 8 surrounding voxel
-// centres.
+// lever arms and no accumulated drift.  Anti-aliasing weights (Sec. 2.2)
+// are the trilinear tent over the 8 surrounding voxel centres.
 //
 // Bounds.  The working volumes carry two zero voxels of padding per side.
 // Per ray and angle the sample range is clipped to padded coordinates
@@ -102,142 +100,6 @@ __device__ inline bool segment(const MarchParams& P, const RayRec& R, double c, 
   return g.k1 > g.k0;
 }
 
-// Position of a sample, clamped into the padded array, its base voxel index
-// and fractional offsets.
-__device__ inline int cell(const MarchParams& P, const Seg& g, float t, float& fx, float& fy,
-                           float& fz) {
-  float x = __builtin_amdgcn_fmed3f(fmaf(t, g.dx, g.gx), 0.0f, P.clx);
-  float y = __builtin_amdgcn_fmed3f(fmaf(t, g.dy, g.gy), 0.0f, P.cly);
-  float z = __builtin_amdgcn_fmed3f(fmaf(t, g.dz, g.gz), 0.0f, P.clz);
-  float ix = floorf(x), iy = floorf(y), iz = floorf(z);
-  fx = x - ix;
-  fy = y - iy;
-  fz = z - iz;
-  return ((int)iz * P.sxy + (int)iy * P.sx) + (int)ix;
-}
-
-// ---------------------------------------------------------------- kernels --
-
-// Forward projection, one lane per (pixel, angle).  Block (64, 4): 64 pixels
-// of 4 consecutive rows; grid (ceil(nu/64), ceil(nv/4), angles).
-template <typename PT>
-__global__ __launch_bounds__(256) void k_forward(MarchParams P, const float* __restrict__ vol,
-                                                 PT* __restrict__ proj) {
-  const int u = blockIdx.x * 64 + threadIdx.x;
-  const int v = blockIdx.y * 4 + threadIdx.y;
-  const int a = blockIdx.z;
-  if (u >= P.nu || v >= P.nv) return;
-  const double2 cs = P.cs[P.a0 + a];
-  const int64_t plane = (int64_t)P.nv * P.nu;
-  float acc = 0.0f;
-  for (int j = 0; j < P.np; ++j) {
-    const RayRec R = P.rays[j * plane + (int64_t)v * P.nu + u];
-    Seg g;
-    if (!segment(P, R, cs.x, cs.y, g)) continue;
-    float sum = 0.0f;
-    float kf = (float)g.k0;
-    for (int k = g.k0; k < g.k1; ++k, kf += 1.0f) {
-      const float t = fmaf(kf, P.step, g.t0);
-      float fx, fy, fz;
-      const float* p = vol + cell(P, g, t, fx, fy, fz);
-      const float v000 = p[0], v001 = p[1];
-      const float v010 = p[P.sx], v011 = p[P.sx + 1];
-      const float v100 = p[P.sxy], v101 = p[P.sxy + 1];
-      const float v110 = p[P.sxy + P.sx], v111 = p[P.sxy + P.sx + 1];
-      const float c00 = fmaf(fx, v001 - v000, v000);
-      const float c01 = fmaf(fx, v011 - v010, v010);
-      const float c10 = fmaf(fx, v101 - v100, v100);
-      const float c11 = fmaf(fx, v111 - v110, v110);
-      const float c0 = fmaf(fy, c01 - c00, c00);
-      const float c1 = fmaf(fy, c11 - c10, c10);
-      const float val = fmaf(fz, c1 - c0, c0);
-      sum = fmaf(exp2f(P.nb * t), val, sum);
-    }
-    acc = fmaf(g.cw, sum, acc);
-  }
-  store_elem(proj, ((int64_t)a * P.nv + v) * P.nu + u, acc);
-}
-
-// Dose deposit, the transpose of k_forward: the same lanes, the same
-// samples and weights, scattered with hardware FP32 atomics into the padded
-// accumulator.  AGG = true keeps the 8 corner sums of the current cell in
-// registers while consecutive samples of a ray stay in one cell and flushes
-// them when the cell changes.
-template <typename PT, bool AGG, typename AT>
-__global__ __launch_bounds__(256) void k_back(MarchParams P, const PT* __restrict__ proj,
-                                              AT* __restrict__ dose) {
-  const int u = blockIdx.x * 64 + threadIdx.x;
-  const int v = blockIdx.y * 4 + threadIdx.y;
-  const int a = blockIdx.z;
-  if (u >= P.nu || v >= P.nv) return;
-  const float pv = load_elem(proj, ((int64_t)a * P.nv + v) * P.nu + u);
-  if (pv == 0.0f) return;
-  const double2 cs = P.cs[P.a0 + a];
-  const int64_t plane = (int64_t)P.nv * P.nu;
-  for (int j = 0; j < P.np; ++j) {
-    const RayRec R = P.rays[j * plane + (int64_t)v * P.nu + u];
-    Seg g;
-    if (!segment(P, R, cs.x, cs.y, g)) continue;
-    const float scale = g.cw * pv;
-    float kf = (float)g.k0;
-    int cur = -1;
-    AT w[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    for (int k = g.k0; k < g.k1; ++k, kf += 1.0f) {
-      const float t = fmaf(kf, P.step, g.t0);
-      float fx, fy, fz;
-      const int i = cell(P, g, t, fx, fy, fz);
-      const float e = scale * exp2f(P.nb * t);
-      const float z1 = e * fz, z0 = e - z1;
-      const float y01 = z0 * fy, y00 = z0 - y01;
-      const float y11 = z1 * fy, y10 = z1 - y11;
-      const float q[8] = {y00 - y00 * fx, y00 * fx, y01 - y01 * fx, y01 * fx,
-                          y10 - y10 * fx, y10 * fx, y11 - y11 * fx, y11 * fx};
-      if (AGG) {
-        if (i != cur) {
-          if (cur >= 0) {
-            AT* d = dose + cur;
-            unsafeAtomicAdd(d, w[0]);
-            unsafeAtomicAdd(d + 1, w[1]);
-            unsafeAtomicAdd(d + P.sx, w[2]);
-            unsafeAtomicAdd(d + P.sx + 1, w[3]);
-            unsafeAtomicAdd(d + P.sxy, w[4]);
-            unsafeAtomicAdd(d + P.sxy + 1, w[5]);
-            unsafeAtomicAdd(d + P.sxy + P.sx, w[6]);
-            unsafeAtomicAdd(d + P.sxy + P.sx + 1, w[7]);
-          }
-          cur = i;
-#pragma unroll
-          for (int c = 0; c < 8; ++c) w[c] = q[c];
-        } else {
-#pragma unroll
-          for (int c = 0; c < 8; ++c) w[c] += q[c];
-        }
-      } else {
-        AT* d = dose + i;
-        unsafeAtomicAdd(d, (AT)q[0]);
-        unsafeAtomicAdd(d + 1, (AT)q[1]);
-        unsafeAtomicAdd(d + P.sx, (AT)q[2]);
-        unsafeAtomicAdd(d + P.sx + 1, (AT)q[3]);
-        unsafeAtomicAdd(d + P.sxy, (AT)q[4]);
-        unsafeAtomicAdd(d + P.sxy + 1, (AT)q[5]);
-        unsafeAtomicAdd(d + P.sxy + P.sx, (AT)q[6]);
-        unsafeAtomicAdd(d + P.sxy + P.sx + 1, (AT)q[7]);
-      }
-    }
-    if (AGG && cur >= 0) {
-      AT* d = dose + cur;
-      unsafeAtomicAdd(d, w[0]);
-      unsafeAtomicAdd(d + 1, w[1]);
-      unsafeAtomicAdd(d + P.sx, w[2]);
-      unsafeAtomicAdd(d + P.sx + 1, w[3]);
-      unsafeAtomicAdd(d + P.sxy, w[4]);
-      unsafeAtomicAdd(d + P.sxy + 1, w[5]);
-      unsafeAtomicAdd(d + P.sxy + P.sx, w[6]);
-      unsafeAtomicAdd(d + P.sxy + P.sx + 1, w[7]);
-    }
-  }
-}
-
 // ---------------------------------------------------- tuned kernels (v2) --
 //
 // Same lanes, samples and weights as above, with cheaper per-sample work:
@@ -315,43 +177,30 @@ __global__ __launch_bounds__(256) void k_forward2(MarchParams P, const float* __
   store_elem(proj, ((int64_t)a * P.nv + v) * P.nu + u, acc);
 }
 
-// Deposit with FP32 buffer atomics (AT = float) or FP64 global atomics
-// (AT = double), aggregating consecutive samples that share a cell.
-template <typename AT>
-__device__ inline void flush8(AT* dose, __amdgpu_buffer_rsrc_t R4, int off, const MarchParams& P,
-                              const AT* w) {
-  if constexpr (sizeof(AT) == 4) {
-    __builtin_amdgcn_raw_ptr_buffer_atomic_fadd_f32(w[0], R4, off, 0, 0);
-    __builtin_amdgcn_raw_ptr_buffer_atomic_fadd_f32(w[1], R4, off + 4, 0, 0);
-    __builtin_amdgcn_raw_ptr_buffer_atomic_fadd_f32(w[2], R4, off, P.sx4, 0);
-    __builtin_amdgcn_raw_ptr_buffer_atomic_fadd_f32(w[3], R4, off + 4, P.sx4, 0);
-    __builtin_amdgcn_raw_ptr_buffer_atomic_fadd_f32(w[4], R4, off, P.sxy4, 0);
-    __builtin_amdgcn_raw_ptr_buffer_atomic_fadd_f32(w[5], R4, off + 4, P.sxy4, 0);
-    __builtin_amdgcn_raw_ptr_buffer_atomic_fadd_f32(w[6], R4, off, P.sxy4 + P.sx4, 0);
-    __builtin_amdgcn_raw_ptr_buffer_atomic_fadd_f32(w[7], R4, off + 4, P.sxy4 + P.sx4, 0);
-  } else {
-    AT* d = dose + (off >> 2);
-    unsafeAtomicAdd(d, w[0]);
-    unsafeAtomicAdd(d + 1, w[1]);
-    unsafeAtomicAdd(d + P.sx, w[2]);
-    unsafeAtomicAdd(d + P.sx + 1, w[3]);
-    unsafeAtomicAdd(d + P.sxy, w[4]);
-    unsafeAtomicAdd(d + P.sxy + 1, w[5]);
-    unsafeAtomicAdd(d + P.sxy + P.sx, w[6]);
-    unsafeAtomicAdd(d + P.sxy + P.sx + 1, w[7]);
-  }
+// Deposit with FP64 global atomics into the padded accumulator, aggregating
+// consecutive samples that share a cell (FP32 atomics would bias the sum by
+// ~1e-5 at ~1e5 deposits per voxel).
+__device__ inline void flush8(double* dose, int off, const MarchParams& P, const double* w) {
+  double* d = dose + (off >> 2);
+  unsafeAtomicAdd(d, w[0]);
+  unsafeAtomicAdd(d + 1, w[1]);
+  unsafeAtomicAdd(d + P.sx, w[2]);
+  unsafeAtomicAdd(d + P.sx + 1, w[3]);
+  unsafeAtomicAdd(d + P.sxy, w[4]);
+  unsafeAtomicAdd(d + P.sxy + 1, w[5]);
+  unsafeAtomicAdd(d + P.sxy + P.sx, w[6]);
+  unsafeAtomicAdd(d + P.sxy + P.sx + 1, w[7]);
 }
 
-template <typename PT, typename AT>
+template <typename PT>
 __global__ __launch_bounds__(256) void k_back2(MarchParams P, const PT* __restrict__ proj,
-                                               AT* __restrict__ dose) {
+                                               double* __restrict__ dose) {
   const int u = blockIdx.x * 64 + threadIdx.x;
   const int v = blockIdx.y * 4 + threadIdx.y;
   const int a = blockIdx.z;
   if (u >= P.nu || v >= P.nv) return;
   const float pv = load_elem(proj, ((int64_t)a * P.nv + v) * P.nu + u);
   if (pv == 0.0f) return;
-  const __amdgpu_buffer_rsrc_t R4 = rsrc(dose, P.vol_bytes);
   const double2 cs = P.cs[P.a0 + a];
   const int64_t plane = (int64_t)P.nv * P.nu;
   for (int j = 0; j < P.np; ++j) {
@@ -361,7 +210,7 @@ __global__ __launch_bounds__(256) void k_back2(MarchParams P, const PT* __restri
     float kf = (float)g.k0;
     float e = g.cw * pv * __builtin_amdgcn_exp2f(P.nb * fmaf(kf, P.step, g.t0));
     int cur = -1;
-    AT w[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    double w[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     for (int k = g.k0; k < g.k1; ++k, kf += 1.0f) {
       const float t = fmaf(kf, P.step, g.t0);
       float fx, fy, fz;
@@ -372,7 +221,7 @@ __global__ __launch_bounds__(256) void k_back2(MarchParams P, const PT* __restri
       const float q[8] = {y00 - y00 * fx, y00 * fx, y01 - y01 * fx, y01 * fx,
                           y10 - y10 * fx, y10 * fx, y11 - y11 * fx, y11 * fx};
       if (off != cur) {
-        if (cur >= 0) flush8<AT>(dose, R4, cur, P, w);
+        if (cur >= 0) flush8(dose, cur, P, w);
         cur = off;
 #pragma unroll
         for (int c = 0; c < 8; ++c) w[c] = q[c];
@@ -382,7 +231,7 @@ __global__ __launch_bounds__(256) void k_back2(MarchParams P, const PT* __restri
       }
       e = fmaf(e, P.r_hi, e * P.r_lo);
     }
-    if (cur >= 0) flush8<AT>(dose, R4, cur, P, w);
+    if (cur >= 0) flush8(dose, cur, P, w);
   }
 }
 
@@ -448,21 +297,19 @@ MarchParams march_params(const vam_geometry* h, int a0) {
   return P;
 }
 
-// The tuned kernels address the padded arrays with 32-bit byte offsets and
-// 24-bit multiplies.
+// The ray-driven references address the padded arrays with 32-bit byte
+// offsets and 24-bit multiplies.
 static bool v2_eligible(const vam_geometry* h) {
   return h->pad_voxels * 8 < 0x7fffffffLL && (int64_t)h->px * h->py * 4 < (1 << 24);
 }
-
-// Kernels used when the caller asks for the default (fastest measured).
-constexpr int kDefaultForwardVariant = 2;
-constexpr int kDefaultBackVariant = 11;
 
 static inline unsigned blocks_for(int64_t n, int threads) { return (unsigned)((n + threads - 1) / threads); }
 
 vam_status launch_forward(vam_geometry* h, const void* vol, vam_dtype vol_t, void* proj,
                           vam_dtype proj_t, int a0, int na, hipStream_t s) {
   const vam_geometry_desc& D = h->desc;
+  if (h->forward_variant == 1 && !v2_eligible(h))
+    return fail(VAM_ERR_UNSUPPORTED, "the ray-driven forward needs a padded volume below 2^28 voxels");
   const int64_t nvox = (int64_t)D.nx * D.ny * D.nz;
   const unsigned vb = blocks_for(nvox, 256);
   switch (vol_t) {
@@ -481,54 +328,31 @@ vam_status launch_forward(vam_geometry* h, const void* vol, vam_dtype vol_t, voi
   }
   VAM_HIP_TRY(hipGetLastError(), "launching the volume copy");
   MarchParams P = march_params(h, a0);
-  dim3 grid((D.n_u + 63) / 64, (D.n_v + 3) / 4, na), block(64, 4);
-  const int fv = h->forward_variant == 0 ? kDefaultForwardVariant : h->forward_variant;
-  const bool v2 = fv == 3 && v2_eligible(h);
   VAM_HIP_TRY(hipEventRecord(h->ev[0], s), "recording an event");
-  if (fv == 2) {
+  if (h->forward_variant == 0) {
     vam_status st = launch_box_forward(h, P, proj, proj_t, na, s);
     if (st != VAM_OK) return st;
-    VAM_HIP_TRY(hipEventRecord(h->ev[1], s), "recording an event");
-    h->ev_valid[0] = 1;
-    return VAM_OK;
+  } else {
+    dim3 grid((D.n_u + 63) / 64, (D.n_v + 3) / 4, na), block(64, 4);
+    switch (proj_t) {
+      case VAM_F32: hipLaunchKernelGGL(k_forward2<float>, grid, block, 0, s, P, h->vol_pad, (float*)proj); break;
+      case VAM_BF16:
+        hipLaunchKernelGGL(k_forward2<uint16_t>, grid, block, 0, s, P, h->vol_pad, (uint16_t*)proj);
+        break;
+      case VAM_F16: hipLaunchKernelGGL(k_forward2<__half>, grid, block, 0, s, P, h->vol_pad, (__half*)proj); break;
+    }
+    VAM_HIP_TRY(hipGetLastError(), "launching the forward projector");
   }
-  switch (proj_t) {
-    case VAM_F32:
-      if (v2) hipLaunchKernelGGL(k_forward2<float>, grid, block, 0, s, P, h->vol_pad, (float*)proj);
-      else hipLaunchKernelGGL(k_forward<float>, grid, block, 0, s, P, h->vol_pad, (float*)proj);
-      break;
-    case VAM_BF16:
-      if (v2) hipLaunchKernelGGL(k_forward2<uint16_t>, grid, block, 0, s, P, h->vol_pad, (uint16_t*)proj);
-      else hipLaunchKernelGGL(k_forward<uint16_t>, grid, block, 0, s, P, h->vol_pad, (uint16_t*)proj);
-      break;
-    case VAM_F16:
-      if (v2) hipLaunchKernelGGL(k_forward2<__half>, grid, block, 0, s, P, h->vol_pad, (__half*)proj);
-      else hipLaunchKernelGGL(k_forward<__half>, grid, block, 0, s, P, h->vol_pad, (__half*)proj);
-      break;
-  }
-  VAM_HIP_TRY(hipGetLastError(), "launching the forward projector");
   VAM_HIP_TRY(hipEventRecord(h->ev[1], s), "recording an event");
   h->ev_valid[0] = 1;
   return VAM_OK;
 }
 
-template <typename PT>
-static void launch_back_t(vam_geometry* h, int variant, const PT* proj, const MarchParams& P, dim3 grid,
-                          dim3 block, hipStream_t s) {
-  switch (variant) {
-    case 1: hipLaunchKernelGGL((k_back<PT, false, float>), grid, block, 0, s, P, proj, h->dose_pad); break;
-    case 2: hipLaunchKernelGGL((k_back<PT, true, float>), grid, block, 0, s, P, proj, h->dose_pad); break;
-    case 3: hipLaunchKernelGGL((k_back<PT, true, double>), grid, block, 0, s, P, proj, h->dose_pad64); break;
-    case 4: hipLaunchKernelGGL((k_back2<PT, float>), grid, block, 0, s, P, proj, h->dose_pad); break;
-    default: hipLaunchKernelGGL((k_back2<PT, double>), grid, block, 0, s, P, proj, h->dose_pad64); break;
-  }
-}
-
 vam_status launch_back(vam_geometry* h, const void* proj, vam_dtype proj_t, float* dose, int accumulate,
                        int a0, int na, hipStream_t s) {
   const vam_geometry_desc& D = h->desc;
-  int variant = h->adjoint_variant == 0 ? kDefaultBackVariant : h->adjoint_variant;
-  if (variant == 9) {
+  const int variant = h->adjoint_variant;
+  if (variant == 2) {
     // voxel-driven gather: writes (or adds to) the output directly
     vam_status st = prepare_gather(h, s);
     if (st != VAM_OK) return st;
@@ -539,39 +363,42 @@ vam_status launch_back(vam_geometry* h, const void* proj, vam_dtype proj_t, floa
     h->ev_valid[1] = 1;
     return VAM_OK;
   }
-  if ((variant == 4 || variant == 5) && !v2_eligible(h)) variant -= 2;
-  const bool wide = variant == 3 || variant == 5 || variant >= 6;
-  if (wide && !h->dose_pad64)
-    VAM_HIP_TRY(hipMalloc(&h->dose_pad64, h->pad_voxels * sizeof(double)), "allocating the FP64 accumulator");
-  if (wide)
-    hipLaunchKernelGGL(k_fill<double>, dim3(blocks_for(h->pad_voxels, 256)), dim3(256), 0, s, h->dose_pad64,
-                       h->pad_voxels, 0.0);
-  else
-    hipLaunchKernelGGL(k_fill<float>, dim3(blocks_for(h->pad_voxels, 256)), dim3(256), 0, s, h->dose_pad,
-                       h->pad_voxels, 0.0f);
+  if (variant == 1 && !v2_eligible(h))
+    return fail(VAM_ERR_UNSUPPORTED, "the ray-driven deposit needs a padded volume below 2^28 voxels");
+  if (!h->boxes_ready && variant == 0)
+    return fail(VAM_ERR_INVALID_ARG, "the box decomposition is not available (a rebuild failed); "
+                                     "set the box edge again or create a new geometry");
+  if (!h->dose_pad64)
+    VAM_HIP_TRY(dev_alloc((void**)&h->dose_pad64, h->pad_voxels * sizeof(double)),
+                "allocating the FP64 accumulator");
+  hipLaunchKernelGGL(k_fill<double>, dim3(blocks_for(h->pad_voxels, 256)), dim3(256), 0, s, h->dose_pad64,
+                     h->pad_voxels, 0.0);
   VAM_HIP_TRY(hipGetLastError(), "launching the accumulator clear");
   MarchParams P = march_params(h, a0);
-  dim3 grid((D.n_u + 63) / 64, (D.n_v + 3) / 4, na), block(64, 4);
   VAM_HIP_TRY(hipEventRecord(h->ev[2], s), "recording an event");
-  if (variant >= 6) {
-    launch_box_deposit(h, P, proj, proj_t, na, variant, s);
+  if (variant == 0) {
+    vam_status st = launch_box_deposit(h, P, proj, proj_t, na, s);
+    if (st != VAM_OK) return st;
   } else {
+    dim3 grid((D.n_u + 63) / 64, (D.n_v + 3) / 4, na), block(64, 4);
     switch (proj_t) {
-      case VAM_F32: launch_back_t(h, variant, (const float*)proj, P, grid, block, s); break;
-      case VAM_BF16: launch_back_t(h, variant, (const uint16_t*)proj, P, grid, block, s); break;
-      case VAM_F16: launch_back_t(h, variant, (const __half*)proj, P, grid, block, s); break;
+      case VAM_F32:
+        hipLaunchKernelGGL(k_back2<float>, grid, block, 0, s, P, (const float*)proj, h->dose_pad64);
+        break;
+      case VAM_BF16:
+        hipLaunchKernelGGL(k_back2<uint16_t>, grid, block, 0, s, P, (const uint16_t*)proj, h->dose_pad64);
+        break;
+      case VAM_F16:
+        hipLaunchKernelGGL(k_back2<__half>, grid, block, 0, s, P, (const __half*)proj, h->dose_pad64);
+        break;
     }
   }
   VAM_HIP_TRY(hipGetLastError(), "launching the dose deposit");
   VAM_HIP_TRY(hipEventRecord(h->ev[3], s), "recording an event");
   h->ev_valid[1] = 1;
   const int64_t nvox = (int64_t)D.nx * D.ny * D.nz;
-  if (wide)
-    hipLaunchKernelGGL(k_unpad<double>, dim3(blocks_for(nvox, 256)), dim3(256), 0, s, h->dose_pad64, dose,
-                       accumulate, D.nx, D.ny, D.nz, h->px, h->py);
-  else
-    hipLaunchKernelGGL(k_unpad<float>, dim3(blocks_for(nvox, 256)), dim3(256), 0, s, h->dose_pad, dose,
-                       accumulate, D.nx, D.ny, D.nz, h->px, h->py);
+  hipLaunchKernelGGL(k_unpad<double>, dim3(blocks_for(nvox, 256)), dim3(256), 0, s, h->dose_pad64, dose,
+                     accumulate, D.nx, D.ny, D.nz, h->px, h->py);
   VAM_HIP_TRY(hipGetLastError(), "launching the dose copy");
   return VAM_OK;
 }

@@ -40,6 +40,18 @@ vam_status hip_check(hipError_t e, const char* what) {
 
 bool valid_handle(const vam_geometry* h) { return h && h->magic == kMagic; }
 
+// Allocation-failure injection (vam_debug_fail_allocations): the countdown
+// reaches zero at the allocation that is made to fail.
+static int g_fail_alloc = 0;
+
+hipError_t dev_alloc(void** p, size_t bytes) {
+  if (g_fail_alloc > 0 && --g_fail_alloc == 0) {
+    *p = nullptr;
+    return hipErrorOutOfMemory;
+  }
+  return hipMalloc(p, bytes);
+}
+
 // ------------------------------------------------------------ device math --
 
 struct TraceParams {
@@ -313,6 +325,7 @@ static vam_status validate(const vam_geometry_desc* d) {
   if (!(2.0 * d->r_inner / d->step < 1e6)) return bad("more than 1e6 samples per ray (2 r_inner / step)");
   if (!(d->step >= 1e-3)) return bad("step must be >= 0.001");
   if (d->flags & ~(uint32_t)VAM_NO_FRESNEL) return bad("unknown flag bits");
+  if ((int64_t)d->n_u * d->n_v * d->n_pupil >= 0x7fffffffLL) return bad("n_u n_v n_pupil must be below 2^31");
   return VAM_OK;
 }
 
@@ -320,9 +333,10 @@ static void free_handle(vam_geometry* h) {
   if (!h) return;
   for (int i = 0; i < 4; ++i)
     if (h->ev[i]) (void)hipEventDestroy(h->ev[i]);
-  void* ptrs[] = {h->rays, h->ray64, h->angle_cs, h->vol_pad, h->dose_pad, h->dose_pad64,
-                  h->segs, h->segs_fwd, h->box_begin, h->box_id, h->ray_nseg, h->seg_part,
-                  h->resid, h->grad, h->dose_tmp, h->loss_part, h->cell_begin, h->gseg};
+  free_boxes(h);
+  free_gather(h);
+  void* ptrs[] = {h->rays, h->ray64, h->angle_cs, h->vol_pad, h->dose_pad64,
+                  h->resid, h->grad, h->dose_tmp, h->loss_part};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   h->magic = 0;
@@ -352,11 +366,9 @@ vam_status vam_setup_geometry(const vam_geometry_desc* desc, hipStream_t stream,
   h->magic = kMagic;
   h->desc = *desc;
   h->adjoint_variant = 0;
-  h->fixed_kernels = 1;
   h->seg_order = 11;  // pixel classes (u mod 3, v mod 2), length-sorted runs (fastest measured)
   h->deposit_threads = 256;
   h->xcd_deposit = 8;  // XCD-aware deposit order, angles in blocks of 8 (fastest measured)
-  h->fwd_cache = 0;
   h->angles.resize(desc->n_angles);
   for (int a = 0; a < desc->n_angles; ++a)
     h->angles[a] = desc->angles_rad ? desc->angles_rad[a] : 2.0 * M_PI * a / desc->n_angles;
@@ -393,13 +405,12 @@ vam_status vam_setup_geometry(const vam_geometry_desc* desc, hipStream_t stream,
   } while (0)
 
   for (int i = 0; i < 4; ++i) SETUP_TRY(hipEventCreate(&h->ev[i]), "creating events");
-  SETUP_TRY(hipMalloc(&h->rays, h->n_rays * sizeof(RayRec)), "allocating the ray table");
-  SETUP_TRY(hipMalloc(&h->ray64, h->n_rays * kRay64Fields * sizeof(double)), "allocating FP64 rays");
-  SETUP_TRY(hipMalloc(&h->angle_cs, desc->n_angles * sizeof(double2)), "allocating angles");
-  SETUP_TRY(hipMalloc(&h->vol_pad, h->pad_voxels * sizeof(float)), "allocating the padded volume");
-  SETUP_TRY(hipMalloc(&h->dose_pad, h->pad_voxels * sizeof(float)), "allocating the padded dose");
-  SETUP_TRY(hipMalloc(&pupil_dev, h->pupil.size() * sizeof(double)), "allocating the pupil table");
-  SETUP_TRY(hipMalloc(&count_dev, sizeof(unsigned long long)), "allocating a counter");
+  SETUP_TRY(dev_alloc((void**)&h->rays, h->n_rays * sizeof(RayRec)), "allocating the ray table");
+  SETUP_TRY(dev_alloc((void**)&h->ray64, h->n_rays * kRay64Fields * sizeof(double)), "allocating FP64 rays");
+  SETUP_TRY(dev_alloc((void**)&h->angle_cs, desc->n_angles * sizeof(double2)), "allocating angles");
+  SETUP_TRY(dev_alloc((void**)&h->vol_pad, h->pad_voxels * sizeof(float)), "allocating the padded volume");
+  SETUP_TRY(dev_alloc((void**)&pupil_dev, h->pupil.size() * sizeof(double)), "allocating the pupil table");
+  SETUP_TRY(dev_alloc((void**)&count_dev, sizeof(unsigned long long)), "allocating a counter");
   SETUP_TRY(hipMemcpyAsync(pupil_dev, h->pupil.data(), h->pupil.size() * sizeof(double),
                            hipMemcpyHostToDevice, stream), "copying the pupil table");
   SETUP_TRY(hipMemcpyAsync(h->angle_cs, cs.data(), cs.size() * sizeof(double2),
@@ -478,47 +489,36 @@ vam_status vam_set_variant(vam_geometry_t h, int32_t op, int32_t variant) {
   clear_error();
   if (!valid_handle(h)) return fail(VAM_ERR_BAD_HANDLE, "not a live geometry handle");
   if (op == 0) {
-    if (variant < 0 || variant > 3) return fail(VAM_ERR_INVALID_ARG, "unknown forward variant %d", variant);
+    if (variant < 0 || variant > 1) return fail(VAM_ERR_INVALID_ARG, "unknown forward variant %d", variant);
     h->forward_variant = variant;
   } else if (op == 1) {
-    if (variant < 0 || variant > 14) return fail(VAM_ERR_INVALID_ARG, "unknown deposit variant %d", variant);
+    if (variant < 0 || variant > 2) return fail(VAM_ERR_INVALID_ARG, "unknown deposit variant %d", variant);
     h->adjoint_variant = variant;
-  } else if (op == 4 || op == 7) {
-    if (variant < 0 || variant > 13) return fail(VAM_ERR_INVALID_ARG, "segment order must be in [0, 13]");
+  } else if (op == 2 || op == 4 || op == 7) {
+    if (op == 2 && !supported_box_edge(variant))
+      return fail(VAM_ERR_INVALID_ARG, "box edge %d is not one of 8, 12, 16", variant);
+    if (op != 2 && (variant < 0 || variant > 13))
+      return fail(VAM_ERR_INVALID_ARG, "segment order must be in [0, 13]");
     VAM_HIP_TRY(hipSetDevice(h->device), "hipSetDevice");
     VAM_HIP_TRY(hipDeviceSynchronize(), "synchronising before rebuilding boxes");
-    free_boxes(h);
-    (op == 4 ? h->seg_order : h->seg_order_fwd) = variant;
+    (op == 2 ? h->box_edge : op == 4 ? h->seg_order : h->seg_order_fwd) = variant;
     return build_boxes(h, nullptr);
   } else if (op == 5) {
     if (variant != 256 && variant != 512) return fail(VAM_ERR_INVALID_ARG, "deposit workgroup size must be 256 or 512");
     h->deposit_threads = variant;
-  } else if (op == 6) {
-    if (variant < 0 || variant > 3) return fail(VAM_ERR_INVALID_ARG, "work order flags must be in [0, 3]");
-    h->xcd_forward = variant & 1;
-    h->xcd_deposit = (variant >> 1) & 1;
-  } else if (op == 10) {
-    if (variant < 0 || variant > 1) return fail(VAM_ERR_INVALID_ARG, "forward cell cache switch must be 0 or 1");
-    h->fwd_cache = variant;
   } else if (op == 8 || op == 9) {
     if (variant < 0 || variant > 4096) return fail(VAM_ERR_INVALID_ARG, "angle block must be in [0, 4096]");
     (op == 8 ? h->xcd_deposit : h->xcd_forward) = variant;
-  } else if (op == 3) {
-    if (variant < 0 || variant > 1) return fail(VAM_ERR_INVALID_ARG, "fixed-footprint switch must be 0 or 1");
-    h->fixed_kernels = variant;
-  } else if (op == 2) {
-    const int emax = max_box_edge(h);
-    if (variant < 4 || variant > emax)
-      return fail(VAM_ERR_INVALID_ARG, "box edge %d outside [4, %d] (the FP64 footprint must fit in LDS)", variant,
-                  emax);
-    VAM_HIP_TRY(hipSetDevice(h->device), "hipSetDevice");
-    VAM_HIP_TRY(hipDeviceSynchronize(), "synchronising before rebuilding boxes");
-    free_boxes(h);
-    h->box_edge = variant;
-    return build_boxes(h, nullptr);
   } else {
     return fail(VAM_ERR_INVALID_ARG, "unknown operator %d", op);
   }
+  return VAM_OK;
+}
+
+vam_status vam_debug_fail_allocations(int32_t n) {
+  clear_error();
+  if (n < 0) return fail(VAM_ERR_INVALID_ARG, "n must be >= 0");
+  g_fail_alloc = n;
   return VAM_OK;
 }
 

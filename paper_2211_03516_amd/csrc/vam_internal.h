@@ -47,6 +47,19 @@ struct BoxGrid {
   int nbx, nby, nbz;
 };
 
+// Compact records of the lab-box segments (structure of arrays, one entry
+// per segment, grouped by box): pw = first sample's lab position relative to
+// its box (x, y from the box centre, z from its bottom face) and that
+// sample's weight (T1 T2 / n_pupil) step exp(-alpha s); dn = lab direction
+// and the sample count (int bits); idx = pixel (deposit order) or
+// partial-sum slot rank * n_rays + ray (forward order).  36 bytes per
+// segment.
+struct SegTable {
+  float4* pw = nullptr;
+  float4* dn = nullptr;
+  int* idx = nullptr;
+};
+
 // Per-launch constants of the marching kernels.
 struct MarchParams {
   const RayRec* rays;
@@ -81,8 +94,7 @@ struct vam_geometry {
   double* ray64;                 // [n_rays][kRay64Fields]
   double2* angle_cs;             // [n_angles] (cos, sin)
   float* vol_pad;                // padded FP32 working volume (forward input)
-  float* dose_pad;               // padded FP32 dose accumulator (adjoint)
-  double* dose_pad64;            // padded FP64 accumulator, allocated on first use
+  double* dose_pad64;            // padded FP64 dose accumulator, allocated on first use
   // optimisation buffers, allocated on first vam_optimize_step
   float* resid;                  // [nz][ny][nx]
   float* grad;                   // [n_angles][n_v][n_u]
@@ -94,25 +106,24 @@ struct vam_geometry {
   int ev_valid[2];
   // lab-box segment decomposition
   int box_edge;                  // box edge in voxels (0: library default)
-  int fixed_kernels;             // 1: use the fixed-footprint box kernels where available
-  int seg_order;                 // deposit order of segments inside a box (see build_boxes)
+  int seg_order;                 // deposit order of segments inside a box (see sort_segments)
   int seg_order_fwd;             // forward order of segments inside a box
-  int deposit_threads;           // workgroup size of the fixed-footprint deposit (256 or 512)
-  int fwd_cache;                 // 1: the fixed-footprint forward keeps the current cell's corners in registers
-  int xcd_forward, xcd_deposit;  // 1: XCD-aware work order for the box kernels
+  int deposit_threads;           // workgroup size of the box deposit (256 or 512)
+  int xcd_forward, xcd_deposit;  // work order of the box kernels (see work_item)
   vam::BoxGrid boxes;
+  int boxes_ready;               // 1 once the decomposition is complete; 0 after a failed rebuild
   int n_boxes;                   // boxes holding at least one segment
   int64_t n_segments;
-  int4* segs;                    // [n_segments], grouped by box, deposit order within a box
-  int4* segs_fwd;                // the same segments in the forward projection's order
+  vam::SegTable seg_dep;         // segment records, deposit order within a box
+  vam::SegTable seg_fwd;         // the same segments in the forward projection's order
   int* ray_nseg;                 // [n_rays] segments per ray
   int max_seg_per_ray;
-  float* seg_part;               // forward partial sums [angles][rank][ray], on first use
+  float* seg_part;               // forward partial sums [angle][rank][ray], on first use
   int seg_part_angles;           // angles per chunk of seg_part
   int* box_begin;                // [n_boxes + 1] segment offsets
   int* box_id;                   // [n_boxes] linear box index (x fastest)
+  int* box_supp;                 // [n_boxes] most samples of the box in any 4 x 4 x 3 block of lab unit cells
   int box_cells;                 // largest rotated-box footprint in cells (LDS)
-  int64_t n_supp;                // most samples in any 4 x 4 x 3 block of lab unit cells
   // inverse ray map of the voxel-driven gather deposit, built on first use
   vam::BoxGrid cells;            // lab-frame unit cells
   int* cell_begin;               // [cells + 1] entry offsets
@@ -131,6 +142,9 @@ vam_status fail(vam_status s, const char* fmt, ...);
 void clear_error();
 bool valid_handle(const vam_geometry* h);
 vam_status hip_check(hipError_t e, const char* what);
+// Every device allocation of the library goes through dev_alloc, so that
+// vam_debug_fail_allocations can make a chosen one fail.
+hipError_t dev_alloc(void** p, size_t bytes);
 
 // projector launches (project.hip)
 vam_status launch_forward(vam_geometry* h, const void* vol, vam_dtype vol_t,
@@ -140,14 +154,16 @@ vam_status launch_back(vam_geometry* h, const void* proj, vam_dtype proj_t,
                        float* dose, int accumulate, int a0, int na,
                        hipStream_t s);
 MarchParams march_params(const vam_geometry* h, int a0);
-// lab-box decomposition and box-tiled deposit (boxes.hip)
+// lab-box decomposition and the box-tiled operators (boxes.hip); build_boxes
+// rebuilds from scratch and leaves boxes_ready = 0 (and nothing allocated)
+// on failure
 vam_status build_boxes(vam_geometry* h, hipStream_t s);
 vam_status launch_box_forward(vam_geometry* h, const MarchParams& P, void* proj, vam_dtype proj_t, int na,
                               hipStream_t s);
-void launch_box_deposit(vam_geometry* h, const MarchParams& P, const void* proj, vam_dtype proj_t, int na,
-                        int variant, hipStream_t s);
+vam_status launch_box_deposit(vam_geometry* h, const MarchParams& P, const void* proj, vam_dtype proj_t,
+                              int na, hipStream_t s);
 void free_boxes(vam_geometry* h);
-int max_box_edge(const vam_geometry* h);
+bool supported_box_edge(int B);
 // voxel-driven gather deposit through the inverse ray map (gather.hip);
 // prepare_gather builds the map on first use (synchronises the stream)
 vam_status prepare_gather(vam_geometry* h, hipStream_t s);

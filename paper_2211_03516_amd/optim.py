@@ -114,24 +114,19 @@ def optimize(target, geom, proj=None, steps=50, lr=None, threshold=0.8, sharpnes
     return proj, hist
 
 
-def optimize_stored(target, geom, proj, steps, lr, dtype, threshold=0.8, sharpness=20.0):
-    """Projected gradient descent with the projections stored in `dtype`
-    (BF16 or FP16) and an FP32 master copy: every step deposits the stored
-    projections (the kernels accumulate in FP32/FP64), and the gradient of
-    the dose-threshold loss returns through the hand-written adjoint (the
-    forward projection, via `Dose`).  Returns (FP32 projections, per-step
-    losses)."""
-    torch_ = torch
-    master = proj.float().clone()
+def optimize_stored(target, geom, proj, steps, lr, threshold=0.8, sharpness=20.0):
+    """Projected gradient descent on projections stored in reduced precision
+    (`proj` in bfloat16 or float16, updated in place): every step is one
+    `vam_optimize_step` on the stored projections -- the deposit reads them
+    as stored, the loss is reduced in FP64, the gradient is FP32 and the
+    updated projections are rounded to the storage type by the library.
+    Returns (proj, per-step losses)."""
+    if proj.dtype not in (torch.bfloat16, torch.float16):
+        raise TypeError("optimize_stored expects bfloat16 or float16 projections")
     hist = []
     for _ in range(steps):
-        stored = master.to(dtype).requires_grad_(True)
-        d = dose(stored, geom)
-        loss = ((torch_.sigmoid(sharpness * (d - threshold)) - target) ** 2).mean()
-        loss.backward()
-        master.sub_(lr * stored.grad.float()).clamp_(min=0.0)
-        hist.append(float(loss.detach()))
-    return master, hist
+        hist.append(geom.optimize_step(target, proj, threshold=threshold, sharpness=sharpness, lr=lr))
+    return proj, hist
 
 
 def _first_step(target, geom, proj, threshold, sharpness, lr0=None, shrink=0.5, tries=12):
@@ -164,7 +159,7 @@ def _main(argv=None):
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--seed0", type=int, default=0)
     ap.add_argument("--storage", default="f32", choices=["f32", "bf16", "f16"],
-                    help="projection storage; bf16/f16 run the autograd loop with an FP32 master copy")
+                    help="projection storage; bf16/f16 keep the projections in that type in the library")
     a = ap.parse_args(argv)
     p = synth.workload(a.workload)
     g = Geometry(p)
@@ -190,10 +185,10 @@ def _main(argv=None):
         else:
             lr = _first_step(tt, g, g0, 0.8, 20.0)
             sdt = {"bf16": torch.bfloat16, "f16": torch.float16}[a.storage]
-            proj, losses = optimize_stored(tt, g, g0, a.steps, lr, sdt)
+            proj, losses = optimize_stored(tt, g, g0.to(sdt), a.steps, lr)
             torch.cuda.synchronize()
             dt = time.perf_counter() - t1
-            e1, r1 = dose_error(g.back(proj.to(sdt)), tt)
+            e1, r1 = dose_error(g.back(proj), tt)
             rec = {"loss_first": losses[0], "loss_last": losses[-1], "dose_error_last": e1,
                    "voxel_error_last": r1, "steps": len(losses)}
         print(json.dumps({"workload": a.workload, "storage": a.storage, "target_seed": a.seed0 + i,

@@ -62,7 +62,9 @@ def test_bad_handles_rejected(L):
     assert L.vam_ray_table_stats(None, ctypes.byref(a), None) == vam.VAM_ERR_BAD_HANDLE
     assert L.vam_forward_project(None, None, 0, None, 0, 0, 1, None) == vam.VAM_ERR_BAD_HANDLE
     assert L.vam_back_project(None, None, 0, None, 0, 0, 1, None) == vam.VAM_ERR_BAD_HANDLE
-    assert L.vam_optimize_step(None, None, None, None, None, None, None) == vam.VAM_ERR_BAD_HANDLE
+    assert L.vam_optimize_step(None, None, None, 0, None, None, None, None) == vam.VAM_ERR_BAD_HANDLE
+    assert L.vam_debug_fail_allocations(-1) == vam.VAM_ERR_INVALID_ARG
+    assert L.vam_debug_fail_allocations(0) == vam.VAM_OK
     assert L.vam_export_rays(None, None) == vam.VAM_ERR_BAD_HANDLE
     assert L.vam_set_variant(None, 1, 0) == vam.VAM_ERR_BAD_HANDLE
     # a pointer to garbage is not a handle either

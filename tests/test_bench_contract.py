@@ -43,9 +43,17 @@ def test_traffic_only_for_the_profiled_sources(monkeypatch):
 def test_counter_rates_follow_the_launch_time(monkeypatch):
     rec = {"fetch_bytes": 3e9, "write_bytes": 1e9, "valu_insts": 1024 * 2.4e9 / 2, "l2_read_bytes": 2e12}
     monkeypatch.setattr(bench, "load_counters", lambda kernel: rec)
-    r = bench.counter_rates("deposit", 1000.0)     # one second
+    r = bench.counter_rates("deposit", 1000.0, 1024 * 2.4e9 * 64)     # one second
     assert r["hbm_GBps"] == 4.0 and r["hbm_frac"] == 4.0 / 8000.0
     assert r["l2_read_TBps"] == 2.0
     assert abs(r["valu_issue_busy"] - 1.0) < 1e-12   # one wave64 instruction per SIMD every 2 cycles
+    assert abs(r["valu_lane_slots_per_sample"] - 0.5) < 1e-12
     monkeypatch.setattr(bench, "load_counters", lambda kernel: None)
-    assert bench.counter_rates("deposit", 1000.0) is None
+    assert bench.counter_rates("deposit", 1000.0, 1) is None
+
+
+def test_roofline_flop_count_matches_its_breakdown():
+    # the per-sample FLOP counts (FMA = 2) are the sums their comment lists
+    fwd = 6 + 3 + 7 * 3 + 2
+    dep = 6 + 3 + 6 + 8 + 8 + 1
+    assert bench.FLOP_PER_SAMPLE == {"forward": fwd, "deposit": dep}

@@ -128,7 +128,7 @@ def test_equalize_u8_matches_definition():
 
 
 def test_bf16_storage_optimisation_tracks_fp32():
-    # c3-style loop with projections stored in BF16 (FP32 master copy):
+    # c3-style loop with the projections stored in BF16 inside the library:
     # same start, same step size, losses within a few percent of FP32
     p = scaled(synth.workload("c1"), n_angles=30)
     t, _ = synth.random_config1_target(64, 32.0, seed=6)
@@ -137,11 +137,48 @@ def test_bf16_storage_optimisation_tracks_fp32():
     g0 = optim.plain_init(tt, g)
     lr = 0.25 * optim._first_step(tt, g, g0, 0.8, 20.0)   # a step size that keeps descending
     p32, h32 = optim.optimize(tt, g, proj=g0.clone(), steps=15, lr=lr)
-    p16, h16 = optim.optimize_stored(tt, g, g0.clone(), 15, lr, torch.bfloat16)
+    p16, h16 = optim.optimize_stored(tt, g, g0.to(torch.bfloat16), 15, lr)
     say("FP32 loss %.5f -> %.5f, BF16 storage %.5f -> %.5f" % (h32[0]["loss"], h32[-1]["loss"], h16[0], h16[-1]))
+    assert p16.dtype == torch.bfloat16
     assert h32[-1]["loss"] < h32[0]["loss"] and h16[-1] < h16[0]
     assert h16[0] == pytest.approx(h32[0]["loss"], rel=2e-2)
     assert h16[-1] == pytest.approx(h32[-1]["loss"], rel=5e-2)
+    g.close()
+
+
+@pytest.mark.parametrize("dt", ["bf16", "f16"])
+def test_reduced_precision_step_matches_oracle(dt):
+    # one vam_optimize_step on projections stored in BF16 / FP16, through the
+    # C ABI: the FP64 loss and the dose of the stored values against the
+    # oracle, and every updated value within one rounding of the oracle's
+    # step g - lr grad taken from the same stored values.  One rounding to
+    # nearest is within u of the value, or within half the subnormal spacing
+    # below the format's smallest normal (FP16: 2^-25; BF16: 2^-134)
+    tdt, u, sub = {"bf16": (torch.bfloat16, 2.0 ** -8, 2.0 ** -134),
+                   "f16": (torch.float16, 2.0 ** -11, 2.0 ** -25)}[dt]
+    p = scaled(synth.workload("c1"), n_angles=24)
+    t, _ = synth.random_config1_target(64, 32.0, seed=8)
+    og = oracle.Geometry(p)
+    P0 = oracle.forward(og, t)
+    D0 = oracle.adjoint(og, P0)
+    g0 = torch.from_numpy(P0 * (1.0 / np.percentile(D0[t > 0], 50))).to(DEV, tdt)
+    gs = g0.double().cpu().numpy()                       # the values as stored
+    loss_o, dose_o, grad_o = oracle.loss_grad(og, t, gs, 20.0, 0.8)
+    g = vam.Geometry(p)
+    gp = g0.clone()
+    dose = torch.empty(g.vol_shape, device=DEV)
+    lr = 0.5
+    loss = g.optimize_step(torch.from_numpy(t).to(DEV), gp, threshold=0.8, sharpness=20.0, lr=lr, dose=dose)
+    want = np.maximum(gs - lr * grad_o, 0.0)
+    got = gp.double().cpu().numpy()
+    err = np.abs(got - want)
+    tol = u * np.abs(want) + sub + 1e-4 * lr * np.abs(grad_o).max()
+    say("%s step: loss gpu %.9e oracle %.9e; worst update error / tolerance %.3f"
+        % (dt, loss, loss_o, float((err / tol).max())))
+    assert loss == pytest.approx(loss_o, rel=1e-5)
+    assert relL2(dose.cpu().numpy(), dose_o) <= 1e-5
+    assert np.all(err <= tol)
+    assert gp.dtype == tdt
     g.close()
 
 

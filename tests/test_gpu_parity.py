@@ -35,6 +35,22 @@ def relL2(x, ref):
     return float(np.linalg.norm(x - ref) / max(np.linalg.norm(ref), 1e-300))
 
 
+def maxrel(x, ref):
+    """Largest element-wise deviation, relative to the largest |ref|."""
+    x = np.asarray(x, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    return float(np.abs(x - ref).max() / max(np.abs(ref).max(), 1e-300))
+
+
+def check(x, ref, tol=1e-5, what=""):
+    """rel-L2 <= tol and every element within tol of the largest |ref|."""
+    e2, em = relL2(x, ref), maxrel(x, ref)
+    say("%s rel-L2 %.3e, max element error %.3e of max |ref|" % (what, e2, em))
+    assert np.isfinite(np.asarray(x, dtype=np.float64)).all()
+    assert e2 <= tol and em <= tol, (what, e2, em)
+    return e2
+
+
 def c2_small(n=64, n_pupil=16, n_angles=24, **kw):
     """c2 optics scaled to n^3: thin lens, 10 deg edge chief ray, 12.2 deg
     divergence, refracting vial."""
@@ -94,9 +110,11 @@ def _parity_case(p, vol, proj_in, tol=1e-5):
     Dg = g.back(to_dev(proj_in)).cpu().numpy()
     Do = oracle.adjoint(og, proj_in)
     e_a = relL2(Dg, Do)
-    say("rel-L2 forward %.3e adjoint %.3e" % (e_f, e_a))
+    say("rel-L2 forward %.3e adjoint %.3e; max element error forward %.3e adjoint %.3e"
+        % (e_f, e_a, maxrel(Pg, Po), maxrel(Dg, Do)))
     assert np.isfinite(Pg).all() and np.isfinite(Dg).all()
     assert e_f <= tol and e_a <= tol
+    assert maxrel(Pg, Po) <= tol and maxrel(Dg, Do) <= tol
     return g, og, Pg, Po
 
 
@@ -204,8 +222,25 @@ def test_c1_full_forward_and_adjoint():
     rng = synth.SplitMix64(1)
     x = rng.uniform(64 ** 3).reshape(64, 64, 64)
     y = rng.uniform(90 * 64 * 64).reshape(90, 64, 64)
-    assert relL2(g.forward(to_dev(x)).cpu().numpy(), oracle.forward(og, x)) <= 1e-5
-    assert relL2(g.back(to_dev(y)).cpu().numpy(), oracle.adjoint(og, y)) <= 1e-5
+    check(g.forward(to_dev(x)).cpu().numpy(), oracle.forward(og, x), what="c1 U[0,1) forward")
+    check(g.back(to_dev(y)).cpu().numpy(), oracle.adjoint(og, y), what="c1 U[0,1) deposit")
+    g.close()
+
+
+def test_vial_wider_than_the_grid():
+    # the resin (R_i 28) is wider than the 48^3 grid (half-width 24) and the
+    # thin-lens rays tilt out through the top and bottom, so samples leave
+    # the grid sideways at angle-dependent places: parity of both operators
+    # and the exact sample count (samples whose stencil touches the grid)
+    p = c2_small(48, n_pupil=4, n_angles=9, r_outer=31.0, r_inner=28.0)
+    rng = synth.SplitMix64(41)
+    x = rng.uniform(48 ** 3).reshape(48, 48, 48)
+    y = rng.uniform(9 * 48 * 48).reshape(9, 48, 48)
+    g, og, *_ = _parity_case(p, x, y)
+    _, samples = g.stats()
+    want = oracle.count_samples(og)
+    say("samples per pass: library %d, oracle %d" % (samples, want))
+    assert samples == want
     g.close()
 
 
@@ -238,7 +273,7 @@ def test_chief_ray_only_null_pupil_and_no_fresnel():
     x = rng.uniform(32 ** 3).reshape(32, 32, 32)
     g = gpu_geom(p)
     Pg = g.forward(to_dev(x)).cpu().numpy()
-    assert relL2(Pg, oracle.forward(oracle.Geometry(po), x)) <= 1e-5
+    check(Pg, oracle.forward(oracle.Geometry(po), x))
     g.close()
 
 
@@ -253,7 +288,7 @@ def test_rays_missing_the_vial():
     P = g.forward(x).cpu().numpy()
     Po = oracle.forward(oracle.Geometry(p), np.ones((16, 16, 16)))
     assert np.isfinite(P).all()
-    assert relL2(P, Po) <= 1e-5
+    check(P, Po)
     assert (P[:, :, :5] == 0).all() and (P[:, :, -5:] == 0).all()
     g.close()
     # a vial narrower than half a pixel: every ray misses
@@ -279,9 +314,9 @@ def test_zero_inputs_and_single_pixel_dmd():
     rng = synth.SplitMix64(17)
     x = rng.uniform(16 ** 3).reshape(16, 16, 16)
     og = oracle.Geometry(p1)
-    assert relL2(g1.forward(to_dev(x)).cpu().numpy(), oracle.forward(og, x)) <= 1e-5
+    check(g1.forward(to_dev(x)).cpu().numpy(), oracle.forward(og, x))
     y = np.array([[[0.7]]])
-    assert relL2(g1.back(to_dev(y)).cpu().numpy(), oracle.adjoint(og, y)) <= 1e-5
+    check(g1.back(to_dev(y)).cpu().numpy(), oracle.adjoint(og, y))
     g1.close()
 
 
@@ -320,16 +355,14 @@ def test_forward_variants_agree():
     rng = synth.SplitMix64(11)
     x = rng.uniform(48 ** 3).reshape(48, 48, 48)
     ref = oracle.forward(oracle.Geometry(p), x)
-    for variant in (vam.FWD_PLAIN, vam.FWD_BOX, vam.FWD_TUNED, vam.FWD_DEFAULT):
-        for cache in (0, 1):
-            g.set_forward_variant(variant)
-            g.set_forward_cache(cache)
-            P1 = g.forward(to_dev(x))
-            P2 = g.forward(to_dev(x))
-            assert torch.equal(P1, P2)              # every variant is deterministic
-            e = relL2(P1.cpu().numpy(), ref)
-            say("forward variant %d cache %d rel-L2 %.3e" % (variant, cache, e))
-            assert e <= 1e-5
+    for variant in (vam.FWD_RAY, vam.FWD_DEFAULT):
+        g.set_forward_variant(variant)
+        P1 = g.forward(to_dev(x))
+        P2 = g.forward(to_dev(x))
+        assert torch.equal(P1, P2)              # every variant is deterministic
+        check(P1.cpu().numpy(), ref, what="forward variant %d" % variant)
+    with pytest.raises(vam.VamError):
+        g.set_forward_variant(2)
     g.close()
 
 
@@ -342,22 +375,15 @@ def test_box_edges_agree():
     og = oracle.Geometry(p)
     Pref = oracle.forward(og, x.double().cpu().numpy())
     Dref = oracle.adjoint(og, y.double().cpu().numpy())
-    for edge in (4, 7, 8, 12, 19, 16):
+    for edge in (8, 16, 12):
         g.set_box_edge(edge)
-        for fixed in (0, 1):
-            g.set_fixed_kernels(fixed)
-            g.set_forward_cache(fixed)
-            for dep in (vam.ADJ_BOX_FP64, vam.ADJ_BOX_AGG, vam.ADJ_BOX_SHARED, vam.ADJ_BOX_INT_AGG,
-                        vam.ADJ_BOX_INT_SHARED, vam.ADJ_BOX_INT):
-                g.set_adjoint_variant(dep)
-                ef = relL2(g.forward(x).cpu().numpy(), Pref)
-                ea = relL2(g.back(y).cpu().numpy(), Dref)
-                say("box edge %d fixed %d deposit %d: forward %.3e deposit %.3e" % (edge, fixed, dep, ef, ea))
-                assert ef <= 1e-5 and ea <= 1e-5
-    g.set_adjoint_variant(vam.ADJ_DEFAULT)
-    # an edge whose footprint cannot fit in LDS is rejected on the host
-    with pytest.raises(vam.VamError):
-        g.set_box_edge(20)
+        check(g.forward(x).cpu().numpy(), Pref, what="box edge %d forward" % edge)
+        check(g.back(y).cpu().numpy(), Dref, what="box edge %d deposit" % edge)
+    # edges without a compiled footprint are rejected on the host
+    for edge in (4, 7, 20):
+        with pytest.raises(vam.VamError):
+            g.set_box_edge(edge)
+    check(g.forward(x).cpu().numpy(), Pref, what="after the rejected edges")
     g.close()
 
 
@@ -367,31 +393,53 @@ def test_adjoint_variants_agree():
     rng = synth.SplitMix64(10)
     y = to_dev(rng.uniform(12 * 48 * 48).reshape(12, 48, 48))
     ref = oracle.adjoint(oracle.Geometry(p), y.cpu().numpy().astype(np.float64))
-    for variant in (vam.ADJ_SCATTER_DIRECT, vam.ADJ_SCATTER_AGGREGATED, vam.ADJ_SCATTER_FP64,
-                    vam.ADJ_TUNED_FP32, vam.ADJ_TUNED_FP64, vam.ADJ_BOX_FP64, vam.ADJ_BOX_FP32,
-                    vam.ADJ_BOX_AGG, vam.ADJ_GATHER, vam.ADJ_BOX_SHARED, vam.ADJ_BOX_INT_AGG,
-                    vam.ADJ_BOX_INT_SHARED, vam.ADJ_BOX_INT, vam.ADJ_BOX_INT_PAIR, vam.ADJ_DEFAULT):
+    for variant in (vam.ADJ_RAY, vam.ADJ_GATHER, vam.ADJ_DEFAULT):
         g.set_adjoint_variant(variant)
-        say("adjoint variant", variant)
-        assert relL2(g.back(y).cpu().numpy(), ref) <= 1e-5
+        check(g.back(y).cpu().numpy(), ref, what="deposit variant %d" % variant)
+    with pytest.raises(vam.VamError):
+        g.set_adjoint_variant(3)
     g.close()
 
 
 @pytest.mark.parametrize("step", [0.3, 1.3, 2.2])
-def test_box_deposits_any_step(step):
-    # corner sharing assumes one cell per step; longer steps flush all eight
+def test_box_kernels_any_step(step):
+    # steps of more than one cell per sample, and many samples per cell
     p = c2_small(40, n_pupil=4, n_angles=8, step=step)
     g = gpu_geom(p)
     rng = synth.SplitMix64(14)
+    x = rng.uniform(40 ** 3).reshape(40, 40, 40)
     y = rng.uniform(8 * 40 * 40).reshape(8, 40, 40)
-    ref = oracle.adjoint(oracle.Geometry(p), y)
-    for variant in (vam.ADJ_BOX_AGG, vam.ADJ_BOX_SHARED, vam.ADJ_BOX_INT_AGG, vam.ADJ_BOX_INT_SHARED,
-                    vam.ADJ_BOX_INT_PAIR):
-        g.set_adjoint_variant(variant)
-        e = relL2(g.back(to_dev(y)).cpu().numpy(), ref)
-        say("step %.1f deposit %d rel-L2 %.3e" % (step, variant, e))
-        assert e <= 1e-5
+    og = oracle.Geometry(p)
+    check(g.forward(to_dev(x)).cpu().numpy(), oracle.forward(og, x), what="step %.1f forward" % step)
+    check(g.back(to_dev(y)).cpu().numpy(), oracle.adjoint(og, y), what="step %.1f deposit" % step)
     g.close()
+
+
+def _n_supp(p):
+    """Most samples of all rays in any 4 x 4 x 3 block of lab-frame unit
+    cells (x, y from -(R_i + 1), z from the padded grid's origin): the count
+    the fixed-point deposit's scale is built on, from the oracle's rays."""
+    R = oracle.trace(oracle.Geometry(p))
+    hit = R[..., oracle.R_HIT] == 1
+    e, d = R[hit][:, oracle.R_E:oracle.R_E + 3], R[hit][:, oracle.R_DR:oracle.R_DR + 3]
+    K = R[hit][:, oracle.R_K].astype(np.int64)
+    ray = np.repeat(np.arange(len(K)), K)
+    k = np.arange(K.sum()) - np.repeat(np.cumsum(K) - K, K)
+    q = e[ray] + ((k + 0.5) * p["step"])[:, None] * d[ray]
+    x0, z0 = -(p["r_inner"] + 1.0), -(0.5 * (p["nz"] - 1) + 2)
+    ncx, ncz = int(math.ceil(2 * (p["r_inner"] + 1.0))), p["nz"] + 4
+    gz = q[:, 2] - z0
+    keep = (gz >= 0.5) & (gz <= p["nz"] + 2.5)      # the samples the kernels march
+    i = np.clip(np.floor(q[keep] - np.array([x0, x0, z0])).astype(np.int64), 0,
+                np.array([ncx - 1, ncx - 1, ncz - 1]))
+    c = np.zeros((ncz, ncx, ncx), dtype=np.int64)
+    np.add.at(c, (i[:, 2], i[:, 1], i[:, 0]), 1)
+    w = np.zeros_like(c)
+    for dz in range(3):
+        for dy in range(4):
+            for dx in range(4):
+                w[:ncz - dz, :ncx - dy, :ncx - dx] += c[dz:, dy:, dx:]
+    return int(w.max())
 
 
 def test_integer_deposit_dynamic_range_and_nonfinite():
@@ -406,48 +454,49 @@ def test_integer_deposit_dynamic_range_and_nonfinite():
     y[2] *= 1e6
     y[4, ::2] *= -1.0
     ref = oracle.adjoint(oracle.Geometry(p), y)
-    for variant in (vam.ADJ_BOX_INT_AGG, vam.ADJ_BOX_INT_SHARED, vam.ADJ_BOX_INT, vam.ADJ_BOX_INT_PAIR,
-                    vam.ADJ_BOX_AGG):
-        g.set_adjoint_variant(variant)
-        D = g.back(to_dev(y)).cpu().numpy()
-        e = relL2(D, ref)
-        # the angles without the 1e6 factor, on their own
-        y_small = y.copy()
-        y_small[2] = 0.0
-        e_small = relL2(g.back(to_dev(y_small)).cpu().numpy(), oracle.adjoint(oracle.Geometry(p), y_small))
-        say("variant %d: rel-L2 %.3e, without the large angle %.3e" % (variant, e, e_small))
-        assert e <= 1e-5 and e_small <= 1e-5
-        bad = y.copy()
-        bad[3, 20, 20] = float("nan")
-        Db = g.back(to_dev(bad)).cpu().numpy()
-        assert np.isnan(Db).any()
+    D = g.back(to_dev(y)).cpu().numpy()
+    check(D, ref, what="dynamic range")
+    # the angles without the 1e6 factor, on their own
+    y_small = y.copy()
+    y_small[2] = 0.0
+    check(g.back(to_dev(y_small)).cpu().numpy(), oracle.adjoint(oracle.Geometry(p), y_small),
+          what="dynamic range without the large angle")
+    bad = y.copy()
+    bad[3, 20, 20] = float("nan")
+    Db = g.back(to_dev(bad)).cpu().numpy()
+    assert np.isnan(Db).any()
     g.close()
 
 
-def test_packed_pair_deposit_matches_32_bit_sums():
-    # variant 14 adds the x-neighbouring corners of a cell as one exact
-    # 64-bit pair: the same rounded values and integer sums as variant 11,
-    # so the two agree up to the free order of the FP64 atomic adds of the
-    # workgroups into the dose; signed inputs exercise the sign handling of
-    # the pair (a negative x corner borrows from the x + 1 half)
-    p = c2_small(40, n_pupil=4, n_angles=10)
-    rng = synth.SplitMix64(17)
-    y_pos = rng.uniform(10 * 40 * 40).reshape(10, 40, 40)
-    y_sgn = 2.0 * rng.uniform(10 * 40 * 40).reshape(10, 40, 40) - 1.0
-    for edge in (8, 12, 16):
-        g = gpu_geom(p)
-        g.set_box_edge(edge)
-        for y in (y_pos, y_sgn):
-            yd = to_dev(y)
-            g.set_adjoint_variant(vam.ADJ_BOX_INT_AGG)
-            D32 = g.back(yd)
-            g.set_adjoint_variant(vam.ADJ_BOX_INT_PAIR)
-            D64 = g.back(yd)
-            dd = float(((D64 - D32).abs() / D32.abs().clamp_min(1e-30)).max())
-            e = relL2(D64.cpu().numpy(), oracle.adjoint(oracle.Geometry(p), y))
-            say("edge %d: pair vs 32-bit max rel diff %.2e, rel-L2 vs oracle %.3e" % (edge, dd, e))
-            assert dd <= 2.0 ** -23 and e <= 1e-5
-        g.close()
+def test_fixed_point_deposit_per_voxel_bound():
+    # A few bright pixels over a dim floor: a dim voxel in a box that a
+    # bright ray crosses is summed at the bright ray's scale.  Per voxel the
+    # fixed-point rounding is bounded by
+    #   sum over angles of n_supp^2 (step / n_pupil) max_a|P| / 2^30
+    # (at most n adds per angle and box, each within 1/(2S) with
+    # S >= 2^30 / (n (step / n_pupil) max|P|), n <= n_supp, the largest
+    # window count of all samples), plus the FP32 rounding of the sample
+    # weights; every voxel is held to that bound.
+    p = c2_small(40, n_pupil=4, n_angles=6)
+    g = gpu_geom(p)
+    rng = synth.SplitMix64(18)
+    y = 1e-4 * rng.uniform(6 * 40 * 40).reshape(6, 40, 40)
+    spots = (rng.uniform(36) * 40).astype(int).reshape(6, 3, 2)
+    for a in range(6):
+        for v, u in spots[a]:
+            y[a, v, u] = 1e4
+    og = oracle.Geometry(p)
+    ref = oracle.adjoint(og, y)
+    D = g.back(to_dev(y)).cpu().numpy().astype(np.float64)
+    ns = _n_supp(p)
+    quant = sum(ns * ns * (p["step"] / p["n_pupil"]) * np.abs(y[a]).max() / 2.0 ** 30 for a in range(6))
+    bound = quant + 1e-6 * np.abs(ref) + 1e-7 * np.abs(ref).max()
+    err = np.abs(D - ref)
+    dim = (ref > 0) & (ref < 1e-3 * ref.max())
+    say("n_supp %d; per-voxel bound from rounding %.3e; worst error / bound %.3e; worst relative error of "
+        "dim voxels %.3e" % (ns, quant, float((err / bound).max()), float((err[dim] / ref[dim]).max())))
+    assert np.all(err <= bound)
+    g.close()
 
 
 def test_work_orders_agree():
@@ -507,11 +556,11 @@ def test_gather_deposit_angles_accumulate_and_order():
     D2 = g.back(to_dev(y[3:8]), angle_begin=3)
     assert torch.equal(D1, D2)
     say("gather sub-range rel-L2 %.3e" % relL2(D1.cpu().numpy(), ref))
-    assert relL2(D1.cpu().numpy(), ref) <= 1e-5
+    check(D1.cpu().numpy(), ref)
     base = to_dev(rng.uniform(40 ** 3).reshape(40, 40, 40))
     acc = base.clone()
     g.back(to_dev(y[3:8]), angle_begin=3, out=acc, accumulate=True)
-    assert relL2((acc - base).cpu().numpy(), ref) <= 1e-5
+    check((acc - base).cpu().numpy(), ref)
     # telecentric, index-matched rays (c1 optics)
     p1 = scaled(synth.workload("c1"), n_angles=20)
     g1 = gpu_geom(p1)
@@ -554,10 +603,10 @@ def c2_full():
     g.close()
 
 
-@pytest.mark.parametrize("variant", ["default", "tuned"])
+@pytest.mark.parametrize("variant", ["default", "ray"])
 def test_c2_full_forward_sampled(c2_full, variant):
     p, t, g = c2_full
-    g.set_forward_variant(vam.FWD_TUNED if variant == "tuned" else vam.FWD_DEFAULT)
+    g.set_forward_variant(vam.FWD_RAY if variant == "ray" else vam.FWD_DEFAULT)
     say("c2 full forward, 360 angles, variant", variant)
     P = g.forward(to_dev(t)).cpu().numpy()
     g.set_forward_variant(vam.FWD_DEFAULT)
@@ -568,23 +617,45 @@ def test_c2_full_forward_sampled(c2_full, variant):
     uu = (rng.uniform(len(ang)) * 256).astype(np.int32)
     ref = oracle.forward_pixels(oracle.Geometry(p), t, ang, vv, uu)
     got = P[ang, vv, uu]
-    e = relL2(got, ref)
-    say("c2 sampled forward rel-L2 %.3e over %d pixels" % (e, len(ang)))
-    assert e <= 1e-5
+    check(got, ref, what="c2 sampled forward (%d pixels)" % len(ang))
 
 
-def test_c2_full_adjoint_one_angle(c2_full):
+def test_c2_full_samples_per_pass_8_angles():
+    # the throughput metric's denominator at the benchmark's optics, on 8
+    # angles spread over the full turn: exact integer agreement
+    p = dict(synth.workload("c2"))
+    p["angles"] = np.array([0, 41, 97, 150, 199, 251, 302, 353]) * (2 * math.pi / 360)
+    p["n_angles"] = 8
+    g = gpu_geom(p)
+    _, samples = g.stats()
+    g.close()
+    want = oracle.count_samples(oracle.Geometry(p))
+    say("c2 samples over 8 angles: library %d, oracle %d" % (samples, want))
+    assert samples == want
+
+
+@pytest.mark.parametrize("a", [0, 61, 137, 199, 263, 331])
+def test_c2_full_adjoint_angles(c2_full, a):
+    # the default deposit of one full 256^2 projection at angles spread over
+    # the turn, against the oracle voxel by voxel
+    p, t, g = c2_full
+    rng = synth.SplitMix64(220 + a)
+    y = rng.uniform(256 * 256).reshape(1, 256, 256)
+    say("c2 full deposit, angle", a)
+    D = g.back(to_dev(y), angle_begin=a).cpu().numpy()
+    check(D, oracle.adjoint(oracle.Geometry(p), y, a0=a, na=1), what="c2 deposit angle %d" % a)
+
+
+def test_c2_full_adjoint_variants_one_angle(c2_full):
     p, t, g = c2_full
     rng = synth.SplitMix64(22)
     y = rng.uniform(256 * 256).reshape(1, 256, 256)
     ref = oracle.adjoint(oracle.Geometry(p), y, a0=37, na=1)
-    for variant in (vam.ADJ_DEFAULT, vam.ADJ_TUNED_FP64, vam.ADJ_GATHER):
+    for variant in (vam.ADJ_RAY, vam.ADJ_GATHER):
         g.set_adjoint_variant(variant)
         say("c2 full adjoint, angle 37, variant", variant)
         D = g.back(to_dev(y), angle_begin=37).cpu().numpy()
-        e = relL2(D, ref)
-        say("c2 one-angle adjoint rel-L2 %.3e" % e)
-        assert e <= 1e-5
+        check(D, ref, what="c2 deposit angle 37 variant %d" % variant)
     g.set_adjoint_variant(vam.ADJ_DEFAULT)
 
 
@@ -646,7 +717,7 @@ def test_c2_full_adjoint_identity(c2_full):
     y = torch.from_numpy(rng.uniform(360 * 256 * 256).reshape(360, 256, 256).astype(np.float32)).to(DEV)
     say("c2 full adjoint identity, 360 angles")
     Ax = g.forward(x).double()
-    g.set_forward_variant(vam.FWD_TUNED)
+    g.set_forward_variant(vam.FWD_RAY)
     Ax_ray = g.forward(x).double()
     g.set_forward_variant(vam.FWD_DEFAULT)
     say("ray-driven forward vs default, rel-L2 %.3e" % float((Ax_ray - Ax).norm() / Ax.norm()))
@@ -654,9 +725,7 @@ def test_c2_full_adjoint_identity(c2_full):
     lhs = float((Ax * y.double()).sum())
     scale = float(Ax.norm() * y.double().norm())
     res = {}
-    for variant in (vam.ADJ_DEFAULT, vam.ADJ_BOX_AGG, vam.ADJ_BOX_FP32, vam.ADJ_TUNED_FP64,
-                    vam.ADJ_SCATTER_AGGREGATED, vam.ADJ_GATHER, vam.ADJ_BOX_SHARED, vam.ADJ_BOX_INT_AGG,
-                    vam.ADJ_BOX_INT_SHARED):
+    for variant in (vam.ADJ_DEFAULT, vam.ADJ_RAY, vam.ADJ_GATHER):
         g.set_adjoint_variant(variant)
         Aty = g.back(y).double()
         rhs = float((x.double() * Aty).sum())
@@ -664,13 +733,9 @@ def test_c2_full_adjoint_identity(c2_full):
         say("variant %d: <Ax,y> %.12e  <x,A^T y> %.12e  rel %.3e  (vs |Ax||y|: %.3e)"
             % (variant, lhs, rhs, res[variant], abs(lhs - rhs) / scale))
     g.set_adjoint_variant(vam.ADJ_DEFAULT)
-    # FP64 accumulation: only the FP32 weights round; FP32 atomics add a
-    # bias that grows with the ~1e5 deposits per voxel
-    # the FP32 forward sums (~7000 terms per pixel) bound the agreement
-    assert res[vam.ADJ_DEFAULT] <= 5e-7 and res[vam.ADJ_TUNED_FP64] <= 5e-7
-    assert res[vam.ADJ_BOX_AGG] <= 5e-7 and res[vam.ADJ_GATHER] <= 5e-7 and res[vam.ADJ_BOX_SHARED] <= 5e-7
-    assert res[vam.ADJ_BOX_INT_AGG] <= 5e-7 and res[vam.ADJ_BOX_INT_SHARED] <= 5e-7
-    assert max(res.values()) <= 5e-5
+    # FP64 accumulation: only the FP32 weights round; the FP32 forward sums
+    # (~7000 terms per pixel) bound the agreement
+    assert max(res.values()) <= 5e-7
 
 
 # --------------------------------------------------- optimisation step ----
@@ -691,7 +756,7 @@ def test_optimize_step_matches_oracle_loss_and_gradient():
     loss = g.optimize_step(to_dev(t), gp, threshold=0.8, sharpness=20.0, lr=lr, dose=dose)
     say("loss gpu %.9e oracle %.9e" % (loss, loss_o))
     assert loss == pytest.approx(loss_o, rel=1e-5)
-    assert relL2(dose.cpu().numpy(), dose_o) <= 1e-5
+    check(dose.cpu().numpy(), dose_o)
     expect = np.maximum(g0 - lr * grad_o, 0)
     # compare the step actually taken, where the clamp is inactive
     step_g = g0 - gp.double().cpu().numpy()
@@ -704,33 +769,80 @@ def test_optimize_step_matches_oracle_loss_and_gradient():
 
 
 # ------------------------------------------------- c4: 512^3 precision ----
+#
+# 512^3, 360 angles, 512^2 DMD, 8 pupil samples, 15 deg edge chief ray.
+# Per-projection error against the FP64 oracle of the volume as given (not
+# as stored): reduced-precision storage rounds the volume once and each
+# projection value once, so for a non-negative volume every projection
+# value is within 2u of the oracle's (u = 2^-8 BF16, 2^-11 FP16), plus the
+# FP32 accumulation; FP32 storage is held to 1e-5.
 
-@pytest.mark.parametrize("dt", ["f32", "bf16", "f16"])
-def test_c4_reduced_precision_64_angles(dt):
-    """512^3, 360 angles, 512^2 DMD, 8 pupil samples: per-projection rel-L2
-    against the FP64 oracle on 64 angles a = floor(k 360 / 64), estimated on
-    64 sampled pixels per angle, for a smooth (non-binary) volume stored in
-    FP32, BF16 or FP16.  Bounds: 1e-5 (FP32), 2u (u = 2^-8, 2^-11)."""
+C4_FULL = [0, 45, 90, 140, 185, 230, 275, 320]          # full 512^2 projections
+C4_ANGLES = [int(k * 360 // 64) for k in range(64)]     # the 64 error angles
+U = {"f32": 0.0, "bf16": 2.0 ** -8, "f16": 2.0 ** -11}
+TDT = {"f32": torch.float32, "bf16": torch.bfloat16, "f16": torch.float16}
+
+
+@pytest.fixture(scope="module")
+def c4_case():
     p = synth.workload("c4")
     n = 512
     t, _ = synth.random_config2_target(n, p["r_inner"], seed=0)
     blob = synth.gaussian_blob_volume((n, n, n), (20.0, -35.0, 10.0), 60.0).astype(np.float32)
     vol = 0.6 * t + 0.4 * blob
-    tdt = {"f32": torch.float32, "bf16": torch.bfloat16, "f16": torch.float16}[dt]
-    bound = {"f32": 1e-5, "bf16": 2 * 2.0 ** -8, "f16": 2 * 2.0 ** -11}[dt]
-    g = gpu_geom(p)
-    say("c4 forward", dt)
-    P = g.forward(to_dev(vol, tdt), out_dtype=tdt).float().cpu().numpy()
-    g.close()
-    angles = [int(k * 360 // 64) for k in range(64)]
+    og = oracle.Geometry(p)
+    say("c4 oracle: %d full projections" % len(C4_FULL))
+    full = {a: oracle.forward(og, vol, a0=a, na=1)[0] for a in C4_FULL}
     rng = synth.SplitMix64(40)
     vv = (rng.uniform(64 * 64) * n).astype(np.int32)
     uu = (rng.uniform(64 * 64) * n).astype(np.int32)
-    ang = np.repeat(angles, 64).astype(np.int32)
-    # the oracle sees the volume as stored
-    vs = torch.from_numpy(vol).to(tdt).float().numpy().astype(np.float64)
-    ref = oracle.forward_pixels(oracle.Geometry(p), vs if dt != "f32" else vol, ang, vv, uu)
-    got = P[ang, vv, uu]
-    per = [relL2(got[i * 64:(i + 1) * 64], ref[i * 64:(i + 1) * 64]) for i in range(64)]
-    say("c4 %s per-projection rel-L2: max %.3e mean %.3e (bound %.3e)" % (dt, max(per), np.mean(per), bound))
-    assert max(per) <= bound
+    ang = np.repeat(C4_ANGLES, 64).astype(np.int32)
+    say("c4 oracle: 64 pixels on each of the 64 error angles")
+    sampled = oracle.forward_pixels(og, vol, ang, vv, uu)
+    g = gpu_geom(p)
+    yield dict(p=p, vol=vol, og=og, full=full, ang=ang, vv=vv, uu=uu, sampled=sampled, g=g)
+    g.close()
+
+
+@pytest.mark.parametrize("dt", ["f32", "bf16", "f16"])
+def test_c4_per_projection_error_64_angles(c4_case, dt):
+    """Per-projection rel-L2 against the FP64 oracle: in full on 8 of the 64
+    error angles, on 64 sampled pixels on every one of them; and each full
+    projection's pixels within 2u of their own value plus 1e-5 of the
+    projection's largest (FP32: within 1e-5 of the largest)."""
+    c = c4_case
+    u = U[dt]
+    bound = 1e-5 if dt == "f32" else 2 * u
+    say("c4 forward", dt)
+    P = c["g"].forward(to_dev(c["vol"], TDT[dt]), out_dtype=TDT[dt]).float().cpu().numpy()
+    per_full = []
+    for a in C4_FULL:
+        ref = c["full"][a]
+        per_full.append(relL2(P[a], ref))
+        err = np.abs(P[a].astype(np.float64) - ref)
+        assert np.all(err <= 2.0 * u * np.abs(ref) + 1e-5 * np.abs(ref).max()), (dt, a)
+    got = P[c["ang"], c["vv"], c["uu"]]
+    per = [relL2(got[i * 64:(i + 1) * 64], c["sampled"][i * 64:(i + 1) * 64]) for i in range(64)]
+    say("c4 %s per-projection rel-L2: full projections max %.3e mean %.3e; 64 angles sampled max %.3e "
+        "mean %.3e (bound %.3e)" % (dt, max(per_full), np.mean(per_full), max(per), np.mean(per), bound))
+    assert max(per_full) <= bound and max(per) <= bound
+
+
+@pytest.mark.parametrize("dt", ["f32", "bf16"])
+def test_c4_deposit_two_angles(c4_case, dt):
+    """Deposit of two full 512^2 projections (U[0,1), stored in FP32 or
+    BF16) against the oracle of the values as given: the rounding of each
+    stored projection value moves each voxel by at most u of its own dose."""
+    c = c4_case
+    u = U[dt]
+    rng = synth.SplitMix64(44)
+    for a in (33, 212):
+        y = rng.uniform(512 * 512).reshape(1, 512, 512)
+        say("c4 deposit", dt, "angle", a)
+        D = c["g"].back(to_dev(y, TDT[dt]), angle_begin=a).cpu().numpy().astype(np.float64)
+        ref = oracle.adjoint(c["og"], y, a0=a, na=1)
+        e2 = relL2(D, ref)
+        em = float((np.abs(D - ref) - u * np.abs(ref)).max() / np.abs(ref).max())
+        say("c4 %s deposit angle %d: rel-L2 %.3e, max element error beyond u|ref| %.3e of max"
+            % (dt, a, e2, em))
+        assert e2 <= (1e-5 if dt == "f32" else 2 * u) and em <= 1e-5
