@@ -12,6 +12,16 @@ dose error than the plain start, the plain start is used (fallback).
 
     python -m paper_2211_03516_amd.learned --train 128 --test 16 --steps 40 --epochs 4
 
+Large runs split the training targets into shards, one process each: shard
+k generates its pairs, trains on them starting from the checkpoint of shard
+k - 1 (parameters, Adam moments and step count, input scales and the
+learning-rate schedule's position; a .npz file) and writes its own; the
+evaluation then loads the last checkpoint:
+
+    python -m paper_2211_03516_amd.learned --train 2000 --shards 5 --shard 0 --save ck0.npz ...
+    python -m paper_2211_03516_amd.learned --train 2000 --shards 5 --shard 1 --resume ck0.npz --save ck1.npz ...
+    python -m paper_2211_03516_amd.learned --eval --test 200 --resume ck4.npz ...
+
 All numerical work runs in libvam's kernels (projector, Ram-Lak, dose error,
 optimisation step, and the network's MFMA kernels); this module sequences
 calls and moves batches between device buffers.
@@ -44,11 +54,11 @@ def starts(target, geom, parallel):
 
 def run_until(target, geom, proj, lr, steps, tol=None, threshold=0.8, sharpness=20.0):
     """Projected gradient steps with a fixed step size; stops once the dose
-    error is at most tol.  Returns (projections, dose errors after each step,
-    seconds)."""
+    error is at most tol.  Returns (projections, dose errors after each
+    step, seconds elapsed after each step)."""
     proj = proj.contiguous()
     dose = torch.empty_like(target)
-    errs = []
+    errs, times = [], []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
@@ -56,10 +66,10 @@ def run_until(target, geom, proj, lr, steps, tol=None, threshold=0.8, sharpness=
                            want_loss=False)
         e, _ = dose_error(dose, target, threshold, sharpness)   # synchronises
         errs.append(e)
+        times.append(time.perf_counter() - t0)
         if tol is not None and e <= tol:
             break
-    torch.cuda.synchronize()
-    return proj, errs, time.perf_counter() - t0
+    return proj, errs, times
 
 
 def final_error(target, geom, proj, threshold=0.8, sharpness=20.0):
@@ -83,26 +93,30 @@ def make_dataset(p, seeds, steps, target_fn, log=None):
         X[i * na:(i + 1) * na, 0] = sino
         X[i * na:(i + 1) * na, 1] = g0
         lr = _first_step(tt, geom, g0, 0.8, 20.0)
-        proj, errs, dt = run_until(tt, geom, g0.clone(), lr, steps)
+        proj, errs, times = run_until(tt, geom, g0.clone(), lr, steps)
         Y[i * na:(i + 1) * na] = proj
         if log:
             log({"target_seed": s, "dose_error_start": errs[0] if errs else None,
-                 "dose_error_end": errs[-1] if errs else None, "s": dt})
+                 "dose_error_end": errs[-1] if errs else None, "s": times[-1] if times else 0.0})
     geom.close()
     par.close()
     return X, Y
 
 
-def train(net, X, Y, epochs, batch, lr=1e-3, seed=0, time_limit=None, log=None):
-    """Adam on shuffled batches (seeded order); returns per-epoch mean loss."""
+def train(net, X, Y, epochs, batch, lr=1e-3, seed=0, time_limit=None, log=None, step0=0, total_steps=None):
+    """Adam on shuffled batches (seeded order) with a cosine decay of the
+    step size over total_steps (default: this call's steps), starting at
+    schedule position step0; returns (per-epoch mean loss, schedule position
+    reached)."""
     n = X.shape[0]
     rng = np.random.default_rng(seed)
     hist = []
     t0 = time.perf_counter()
     xb = torch.empty((batch,) + tuple(X.shape[1:]), device=X.device)
     yb = torch.empty((batch,) + tuple(Y.shape[1:]), device=Y.device)
-    total_steps = epochs * (n // batch)
-    step = 0
+    if total_steps is None:
+        total_steps = step0 + epochs * (n // batch)
+    step = step0
     for ep in range(epochs):
         order = torch.from_numpy(rng.permutation(n)).to(X.device)
         losses = []
@@ -126,7 +140,7 @@ def train(net, X, Y, epochs, batch, lr=1e-3, seed=0, time_limit=None, log=None):
         if time_limit and time.perf_counter() - t0 > time_limit:
             break
     torch.cuda.synchronize()
-    return hist
+    return hist, step
 
 
 def infer(net, x, batch):
@@ -157,8 +171,12 @@ def evaluate(net, p, seeds, steps, target_fn, batch, log=None):
         t2 = time.perf_counter()
         e_plain0 = final_error(tt, geom, g0)     # needed by the fallback test only
         t_e0 = time.perf_counter() - t2
-        _, errs_p, sec_p = run_until(tt, geom, g0.clone(), lr, steps)
+        _, errs_p, times_p = run_until(tt, geom, g0.clone(), lr, steps)
         target_err = errs_p[-1]
+        # the plain method is charged up to the first step at which its dose
+        # error reached its final value (the error need not fall
+        # monotonically: it is not the loss being minimised)
+        plain_steps = next(i for i, e in enumerate(errs_p) if e <= target_err) + 1
         # learned start: network inference on (sino, g0), fallback if worse
         torch.cuda.synchronize()
         t1 = time.perf_counter()
@@ -172,13 +190,14 @@ def evaluate(net, p, seeds, steps, target_fn, batch, log=None):
         fallback = not (e_learn0 <= e_plain0)
         t_infer_check = time.perf_counter() - t1
         start = g0.clone() if fallback else gl
-        _, errs_l, sec_l = run_until(tt, geom, start, lr, steps, tol=target_err)
+        _, errs_l, times_l = run_until(tt, geom, start, lr, steps, tol=target_err)
         reached = bool(errs_l) and errs_l[-1] <= target_err
         row = {"target_seed": s, "dose_error_plain_start": e_plain0, "dose_error_learned_start": e_learn0,
                "fallback": fallback, "target_dose_error": target_err,
-               "plain_steps": len(errs_p), "plain_s": t_plain_start + sec_p,
+               "plain_steps": plain_steps, "plain_s": t_plain_start + times_p[plain_steps - 1],
                "learned_steps": len(errs_l), "learned_reached": reached,
-               "learned_s": t_plain_start + t_e0 + t_infer_check + sec_l, "inference_s": t_infer}
+               "learned_s": t_plain_start + t_e0 + t_infer_check + times_l[-1], "inference_s": t_infer,
+               "plain_dose_errors": errs_p}
         rows.append(row)
         if log:
             log(row)
@@ -200,15 +219,29 @@ def summarise(rows):
             "mean_dose_error_learned_start": float(np.mean([r["dose_error_learned_start"] for r in rows]))}
 
 
+def save_checkpoint(path, net, step, total_steps, s0, s1, meta):
+    state, adam_t = net.get_state()
+    np.savez(path, state=state, adam_steps=np.int64(adam_t), step=np.int64(step),
+             total_steps=np.int64(total_steps), scales=np.array([s0, s1], dtype=np.float64),
+             meta=np.frombuffer(json.dumps(meta).encode(), dtype=np.uint8))
+
+
+def load_checkpoint(path):
+    with np.load(path, allow_pickle=False) as z:
+        return {"state": z["state"], "adam_steps": int(z["adam_steps"]), "step": int(z["step"]),
+                "total_steps": int(z["total_steps"]), "s0": float(z["scales"][0]), "s1": float(z["scales"][1]),
+                "meta": json.loads(bytes(z["meta"]).decode())}
+
+
 def main(argv=None):
     import argparse
     import synth
     ap = argparse.ArgumentParser()
     ap.add_argument("--workload", default="c5")
-    ap.add_argument("--train", type=int, default=128)
+    ap.add_argument("--train", type=int, default=128, help="training targets (over all shards)")
     ap.add_argument("--test", type=int, default=16)
     ap.add_argument("--steps", type=int, default=40, help="plain optimisation steps (labels and reference)")
-    ap.add_argument("--epochs", type=int, default=4)
+    ap.add_argument("--epochs", type=int, default=4, help="epochs over each shard")
     ap.add_argument("--batch", type=int, default=16)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--layers", type=int, default=6)
@@ -216,6 +249,11 @@ def main(argv=None):
     ap.add_argument("--train-seconds", type=float, default=0.0)
     ap.add_argument("--scale", type=int, default=0, help="grid/DMD size override (0: the workload's)")
     ap.add_argument("--angles", type=int, default=0)
+    ap.add_argument("--shards", type=int, default=1, help="split the training targets into this many shards")
+    ap.add_argument("--shard", type=int, default=-1, help="generate and train on this shard only")
+    ap.add_argument("--eval", action="store_true", help="only evaluate the network of --resume")
+    ap.add_argument("--resume", default="", help="checkpoint to start from")
+    ap.add_argument("--save", default="", help="checkpoint to write after training")
     a = ap.parse_args(argv)
 
     def log(d):
@@ -229,21 +267,53 @@ def main(argv=None):
                                  r_outer=p["r_outer"] * ratio, r_inner=p["r_inner"] * ratio,
                                  focus=p["focus"] * ratio, pupil=p["pupil"] * ratio)
     fn = synth.random_config2_target
-    t0 = time.perf_counter()
-    X, Y = make_dataset(p, list(range(1000, 1000 + a.train)), a.steps, fn, log=log)
-    log({"phase": "data", "images": int(X.shape[0]), "s": time.perf_counter() - t0})
-    s0 = 1.0 / max(float(X[:, 0].abs().max()), 1e-30)
-    s1 = 1.0 / max(float(X[:, 1].abs().mean()), 1e-30)
-    na, nv, nu = X.shape[0] // a.train, X.shape[2], X.shape[3]
-    net = Cnn(a.layers, a.channels, nv, nu, max_batch=a.batch, in_scale=(s0, s1))
-    net.set_params(synth.cnninit.he_init(a.layers, a.channels, seed=0))
-    t1 = time.perf_counter()
-    hist = train(net, X, Y, a.epochs, a.batch, lr=a.lr, time_limit=a.train_seconds or None, log=log)
-    log({"phase": "train", "epochs": len(hist), "s": time.perf_counter() - t1, "images_per_s":
-         len(hist) * (X.shape[0] // a.batch) * a.batch / (time.perf_counter() - t1)})
-    del X, Y
-    rows = evaluate(net, p, list(range(5000, 5000 + a.test)), a.steps, fn, a.batch, log=log)
-    log({"phase": "summary", **summarise(rows)})
+    ck = load_checkpoint(a.resume) if a.resume else None
+    nv, nu, na = p["nv"], p["nu"], p["n_angles"]
+    net = None
+    if not a.eval:
+        shards = range(a.shards) if a.shard < 0 else [a.shard]
+        per = (a.train + a.shards - 1) // a.shards
+        step = ck["step"] if ck else 0
+        # the cosine schedule spans every shard's epochs
+        total = ck["total_steps"] if ck else a.shards * a.epochs * ((per * na) // a.batch)
+        for k in shards:
+            seeds = list(range(1000 + k * per, 1000 + min((k + 1) * per, a.train)))
+            t0 = time.perf_counter()
+            X, Y = make_dataset(p, seeds, a.steps, fn, log=log)
+            log({"phase": "data", "shard": k, "targets": len(seeds), "images": int(X.shape[0]),
+                 "s": time.perf_counter() - t0})
+            if net is None:
+                if ck:
+                    s0, s1 = ck["s0"], ck["s1"]
+                else:
+                    # input scales from the first shard, kept for all later ones
+                    s0 = 1.0 / max(float(X[:, 0].abs().max()), 1e-30)
+                    s1 = 1.0 / max(float(X[:, 1].abs().mean()), 1e-30)
+                net = Cnn(a.layers, a.channels, nv, nu, max_batch=a.batch, in_scale=(s0, s1))
+                if ck:
+                    net.set_state(ck["state"], ck["adam_steps"])
+                else:
+                    net.set_params(synth.cnninit.he_init(a.layers, a.channels, seed=0))
+            t1 = time.perf_counter()
+            hist, step = train(net, X, Y, a.epochs, a.batch, lr=a.lr, seed=k,
+                               time_limit=a.train_seconds or None, log=log, step0=step, total_steps=total)
+            log({"phase": "train", "shard": k, "epochs": len(hist), "s": time.perf_counter() - t1,
+                 "images_per_s": len(hist) * (X.shape[0] // a.batch) * a.batch / (time.perf_counter() - t1),
+                 "schedule_step": step, "schedule_total": total})
+            del X, Y
+        if a.save:
+            save_checkpoint(a.save, net, step, total, net.in_scale[0], net.in_scale[1],
+                            {"workload": a.workload, "train": a.train, "shards": a.shards, "steps": a.steps,
+                             "epochs": a.epochs, "last_shard": shards[-1]})
+            log({"phase": "checkpoint", "path": a.save, "schedule_step": step})
+    else:
+        if not ck:
+            raise SystemExit("--eval needs --resume")
+        net = Cnn(a.layers, a.channels, nv, nu, max_batch=a.batch, in_scale=(ck["s0"], ck["s1"]))
+        net.set_state(ck["state"], ck["adam_steps"])
+    if a.test > 0 and (a.eval or a.shard < 0):
+        rows = evaluate(net, p, list(range(5000, 5000 + a.test)), a.steps, fn, a.batch, log=log)
+        log({"phase": "summary", **summarise(rows)})
     net.close()
     return 0
 
