@@ -140,6 +140,23 @@ vam_status vam_back_project(vam_geometry_t h, const void* proj, vam_dtype proj_t
                             int32_t angle_begin, int32_t angle_count,
                             hipStream_t stream);
 
+/* vam_back_project without device allocation, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid it).  Same arguments, operator and result as
+ * vam_back_project; the padded FP64 accumulator of the deposit comes from a
+ * file-scope device array of the library (136 MiB per device, held by every
+ * device the library runs on until the process ends) instead of the
+ * handle.  Limit: the padded grid (nx+4)(ny+4)(nz+4) must be at most
+ * 17,825,792 voxels (cubes up to 257^3), else VAM_ERR_UNSUPPORTED; the
+ * gather variant (vam_set_variant op 1 = 2) is refused the same way.  All
+ * calls on one device share the array and it keeps the last call's
+ * contents (each call clears it first, with a kernel): calls that overlap
+ * on one device race.  Errors as for vam_back_project. */
+vam_status vam_back_project_noalloc(vam_geometry_t h, const void* proj, vam_dtype proj_t,
+                                    float* dose, int32_t accumulate,
+                                    int32_t angle_begin, int32_t angle_count,
+                                    hipStream_t stream);
+
 /* One projected gradient step of the dose-threshold loss, standing in for
  * the paper's iterative projection optimisation (Sec. 2.7), over all
  * angles:

@@ -86,6 +86,7 @@ def lib():
             "vam_destroy_geometry": [_P],
             "vam_forward_project": [_P, _P, _I32, _P, _I32, _I32, _I32, _P],
             "vam_back_project": [_P, _P, _I32, _P, _I32, _I32, _I32, _P],
+            "vam_back_project_noalloc": [_P, _P, _I32, _P, _I32, _I32, _I32, _P],
             "vam_optimize_step": [_P, _P, _P, _I32, _P, ctypes.POINTER(OptParams), _DP, _P],
             "vam_debug_fail_allocations": [_I32],
             "vam_ray_table_stats": [_P, _I64P, _I64P],

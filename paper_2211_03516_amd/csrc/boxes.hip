@@ -937,34 +937,36 @@ __global__ __launch_bounds__(NT) void k_back_box(MarchParams P, BoxParams Bp, co
 }
 
 template <int B, typename PT>
-static void launch_back_box(vam_geometry* h, const MarchParams& P, const PT* proj, int na, hipStream_t s) {
+static void launch_back_box(vam_geometry* h, const MarchParams& P, const PT* proj, int na, double* acc,
+                            hipStream_t s) {
   const BoxParams Bp = box_params(h, h->seg_dep, na, h->xcd_deposit);
   const dim3 grid = work_grid(h->n_boxes, na, Bp.xcd);
   if (h->deposit_threads == 512)
-    hipLaunchKernelGGL((k_back_box<B, PT, 512>), grid, dim3(512), 0, s, P, Bp, proj, h->dose_pad64);
+    hipLaunchKernelGGL((k_back_box<B, PT, 512>), grid, dim3(512), 0, s, P, Bp, proj, acc);
   else
-    hipLaunchKernelGGL((k_back_box<B, PT, 256>), grid, dim3(256), 0, s, P, Bp, proj, h->dose_pad64);
+    hipLaunchKernelGGL((k_back_box<B, PT, 256>), grid, dim3(256), 0, s, P, Bp, proj, acc);
 }
 
 template <typename PT>
-static void launch_back_box_t(vam_geometry* h, const MarchParams& P, const PT* proj, int na, hipStream_t s) {
+static void launch_back_box_t(vam_geometry* h, const MarchParams& P, const PT* proj, int na, double* acc,
+                              hipStream_t s) {
   switch (h->boxes.B) {
-    case 8: launch_back_box<8, PT>(h, P, proj, na, s); break;
-    case 12: launch_back_box<12, PT>(h, P, proj, na, s); break;
-    default: launch_back_box<16, PT>(h, P, proj, na, s); break;
+    case 8: launch_back_box<8, PT>(h, P, proj, na, acc, s); break;
+    case 12: launch_back_box<12, PT>(h, P, proj, na, acc, s); break;
+    default: launch_back_box<16, PT>(h, P, proj, na, acc, s); break;
   }
 }
 
 vam_status launch_box_deposit(vam_geometry* h, const MarchParams& P, const void* proj, vam_dtype proj_t, int na,
-                              hipStream_t s) {
+                              double* acc, hipStream_t s) {
   if (!h->boxes_ready)
     return fail(VAM_ERR_INVALID_ARG, "the box decomposition is not available (a rebuild failed); "
                                      "set the box edge again or create a new geometry");
   if (h->n_boxes == 0) return VAM_OK;
   switch (proj_t) {
-    case VAM_F32: launch_back_box_t(h, P, (const float*)proj, na, s); break;
-    case VAM_BF16: launch_back_box_t(h, P, (const uint16_t*)proj, na, s); break;
-    case VAM_F16: launch_back_box_t(h, P, (const __half*)proj, na, s); break;
+    case VAM_F32: launch_back_box_t(h, P, (const float*)proj, na, acc, s); break;
+    case VAM_BF16: launch_back_box_t(h, P, (const uint16_t*)proj, na, acc, s); break;
+    case VAM_F16: launch_back_box_t(h, P, (const __half*)proj, na, acc, s); break;
   }
   return VAM_OK;
 }

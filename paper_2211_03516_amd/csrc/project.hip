@@ -25,6 +25,7 @@
 // corners stay inside the padded array whatever the rounding.
 
 #include <cmath>
+#include <mutex>
 
 #include "vam_internal.h"
 
@@ -349,7 +350,7 @@ vam_status launch_forward(vam_geometry* h, const void* vol, vam_dtype vol_t, voi
 }
 
 vam_status launch_back(vam_geometry* h, const void* proj, vam_dtype proj_t, float* dose, int accumulate,
-                       int a0, int na, hipStream_t s) {
+                       int a0, int na, hipStream_t s, double* acc) {
   const vam_geometry_desc& D = h->desc;
   const int variant = h->adjoint_variant;
   if (variant == 2) {
@@ -368,28 +369,32 @@ vam_status launch_back(vam_geometry* h, const void* proj, vam_dtype proj_t, floa
   if (!h->boxes_ready && variant == 0)
     return fail(VAM_ERR_INVALID_ARG, "the box decomposition is not available (a rebuild failed); "
                                      "set the box edge again or create a new geometry");
-  if (!h->dose_pad64)
-    VAM_HIP_TRY(dev_alloc((void**)&h->dose_pad64, h->pad_voxels * sizeof(double)),
-                "allocating the FP64 accumulator");
-  hipLaunchKernelGGL(k_fill<double>, dim3(blocks_for(h->pad_voxels, 256)), dim3(256), 0, s, h->dose_pad64,
-                     h->pad_voxels, 0.0);
+  if (!acc) {
+    if (!h->dose_pad64)
+      VAM_HIP_TRY(dev_alloc((void**)&h->dose_pad64, h->pad_voxels * sizeof(double)),
+                  "allocating the FP64 accumulator");
+    acc = h->dose_pad64;
+  }
+  // cleared by a kernel (no memset node when the caller captures a graph)
+  hipLaunchKernelGGL(k_fill<double>, dim3(blocks_for(h->pad_voxels, 256)), dim3(256), 0, s, acc, h->pad_voxels,
+                     0.0);
   VAM_HIP_TRY(hipGetLastError(), "launching the accumulator clear");
   MarchParams P = march_params(h, a0);
   VAM_HIP_TRY(hipEventRecord(h->ev[2], s), "recording an event");
   if (variant == 0) {
-    vam_status st = launch_box_deposit(h, P, proj, proj_t, na, s);
+    vam_status st = launch_box_deposit(h, P, proj, proj_t, na, acc, s);
     if (st != VAM_OK) return st;
   } else {
     dim3 grid((D.n_u + 63) / 64, (D.n_v + 3) / 4, na), block(64, 4);
     switch (proj_t) {
       case VAM_F32:
-        hipLaunchKernelGGL(k_back2<float>, grid, block, 0, s, P, (const float*)proj, h->dose_pad64);
+        hipLaunchKernelGGL(k_back2<float>, grid, block, 0, s, P, (const float*)proj, acc);
         break;
       case VAM_BF16:
-        hipLaunchKernelGGL(k_back2<uint16_t>, grid, block, 0, s, P, (const uint16_t*)proj, h->dose_pad64);
+        hipLaunchKernelGGL(k_back2<uint16_t>, grid, block, 0, s, P, (const uint16_t*)proj, acc);
         break;
       case VAM_F16:
-        hipLaunchKernelGGL(k_back2<__half>, grid, block, 0, s, P, (const __half*)proj, h->dose_pad64);
+        hipLaunchKernelGGL(k_back2<__half>, grid, block, 0, s, P, (const __half*)proj, acc);
         break;
     }
   }
@@ -397,9 +402,35 @@ vam_status launch_back(vam_geometry* h, const void* proj, vam_dtype proj_t, floa
   VAM_HIP_TRY(hipEventRecord(h->ev[3], s), "recording an event");
   h->ev_valid[1] = 1;
   const int64_t nvox = (int64_t)D.nx * D.ny * D.nz;
-  hipLaunchKernelGGL(k_unpad<double>, dim3(blocks_for(nvox, 256)), dim3(256), 0, s, h->dose_pad64, dose,
-                     accumulate, D.nx, D.ny, D.nz, h->px, h->py);
+  hipLaunchKernelGGL(k_unpad<double>, dim3(blocks_for(nvox, 256)), dim3(256), 0, s, acc, dose, accumulate,
+                     D.nx, D.ny, D.nz, h->px, h->py);
   VAM_HIP_TRY(hipGetLastError(), "launching the dose copy");
+  return VAM_OK;
+}
+
+// ------------------------------------------------ allocation-free deposit --
+//
+// vam_back_project_noalloc takes the deposit's padded FP64 accumulator from
+// this file-scope device array instead of allocating it.  Each device that
+// loads the library holds its own copy until the process ends; its device
+// address is looked up once per device (with that device current) and kept
+// in scratch_dev, which is what host code passes to the kernels.
+constexpr int64_t kScratchDoubles = 17825792;  // 136 MiB: padded grids up to 261^3 (volumes up to 257^3)
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) double scratch[kScratchDoubles];
+static double* scratch_dev[kMaxDevices];
+static std::mutex scratch_mutex;
+
+static vam_status scratch_for(int device, double** out) {
+  if (device < 0 || device >= kMaxDevices) return fail(VAM_ERR_UNSUPPORTED, "device index %d >= %d", device, kMaxDevices);
+  std::lock_guard<std::mutex> lock(scratch_mutex);
+  if (!scratch_dev[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return hip_check(e != hipSuccess ? e : hipErrorInvalidSymbol, "looking up the scratch array");
+    scratch_dev[device] = (double*)p;
+  }
+  *out = scratch_dev[device];
   return VAM_OK;
 }
 
@@ -438,6 +469,26 @@ vam_status vam_back_project(vam_geometry_t h, const void* proj, vam_dtype proj_t
   if (st != VAM_OK) return st;
   VAM_HIP_TRY(hipSetDevice(h->device), "hipSetDevice");
   return launch_back(h, proj, proj_t, dose, accumulate, angle_begin, angle_count, stream);
+}
+
+vam_status vam_back_project_noalloc(vam_geometry_t h, const void* proj, vam_dtype proj_t, float* dose,
+                                    int32_t accumulate, int32_t angle_begin, int32_t angle_count,
+                                    hipStream_t stream) {
+  clear_error();
+  vam_status st = check_common(h, proj, dose, proj_t, angle_begin, angle_count);
+  if (st != VAM_OK) return st;
+  if (h->pad_voxels > kScratchDoubles)
+    return fail(VAM_ERR_UNSUPPORTED,
+                "allocation-free deposit: the padded grid (%d x %d x %d = %lld voxels) exceeds the %lld-voxel "
+                "scratch array (volumes up to 257^3)",
+                h->px, h->py, h->pz, (long long)h->pad_voxels, (long long)kScratchDoubles);
+  if (h->adjoint_variant == 2)
+    return fail(VAM_ERR_UNSUPPORTED, "allocation-free deposit: the gather variant builds an inverse ray map");
+  VAM_HIP_TRY(hipSetDevice(h->device), "hipSetDevice");
+  double* acc = nullptr;
+  st = scratch_for(h->device, &acc);
+  if (st != VAM_OK) return st;
+  return launch_back(h, proj, proj_t, dose, accumulate, angle_begin, angle_count, stream, acc);
 }
 
 vam_status vam_kernel_times(vam_geometry_t h, float* forward_ms, float* back_ms) {

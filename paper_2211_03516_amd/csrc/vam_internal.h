@@ -150,9 +150,11 @@ hipError_t dev_alloc(void** p, size_t bytes);
 vam_status launch_forward(vam_geometry* h, const void* vol, vam_dtype vol_t,
                           void* proj, vam_dtype proj_t, int a0, int na,
                           hipStream_t s);
+// acc: the padded FP64 accumulator to use (pad_voxels doubles), or NULL for
+// the handle's own (allocated on first use)
 vam_status launch_back(vam_geometry* h, const void* proj, vam_dtype proj_t,
                        float* dose, int accumulate, int a0, int na,
-                       hipStream_t s);
+                       hipStream_t s, double* acc = nullptr);
 MarchParams march_params(const vam_geometry* h, int a0);
 // lab-box decomposition and the box-tiled operators (boxes.hip); build_boxes
 // rebuilds from scratch and leaves boxes_ready = 0 (and nothing allocated)
@@ -161,7 +163,7 @@ vam_status build_boxes(vam_geometry* h, hipStream_t s);
 vam_status launch_box_forward(vam_geometry* h, const MarchParams& P, void* proj, vam_dtype proj_t, int na,
                               hipStream_t s);
 vam_status launch_box_deposit(vam_geometry* h, const MarchParams& P, const void* proj, vam_dtype proj_t,
-                              int na, hipStream_t s);
+                              int na, double* acc, hipStream_t s);
 void free_boxes(vam_geometry* h);
 bool supported_box_edge(int B);
 // voxel-driven gather deposit through the inverse ray map (gather.hip);
