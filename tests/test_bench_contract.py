@@ -23,7 +23,8 @@ def test_more_than_one_gpu_is_refused():
 def test_learned_vs_plain_comes_from_the_committed_run():
     d = bench.learned_vs_plain()
     assert d is not None and d["source"] == "profiles/learned_c5.txt"
-    assert d["command"].startswith("python -u -m paper_2211_03516_amd.learned")
+    assert d["commands"] and all(c.startswith("python -u -m paper_2211_03516_amd.learned") for c in d["commands"])
+    assert d["timed_here"] is False
     assert 0 < d["learned_steps"] <= d["plain_steps"] and d["learned_s"] > 0 and d["plain_s"] > 0
     # the summary line in the file is the one reported
     summary = [json.loads(l) for l in open(os.path.join(ROOT, "profiles", "learned_c5.txt"))
