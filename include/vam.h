@@ -233,7 +233,14 @@ vam_status vam_export_rays(vam_geometry_t h, double* out);
  *   op 0, forward:  0 = default: lab-box tiled, volume footprint staged in
  *                   LDS, deterministic per-segment partial sums;
  *                   1 = ray-driven reference (one lane per pixel and angle,
- *                   buffer gathers from the padded volume).
+ *                   buffer gathers from the padded volume);
+ *                   2 = lab-box tiled, each segment's partial added to its
+ *                   pixel as a 64-bit integer (scale: a power of two from
+ *                   the volume's largest |value| and the most samples of a
+ *                   pixel; rounding <= 2^-62 of that bound per add; integer
+ *                   adds make it deterministic); a NaN or infinity anywhere
+ *                   in the volume makes every projection value NaN.  Needs
+ *                   n_angles x n_u x n_v x 8 bytes, allocated on first use.
  *   op 1, deposit:  0 = default: lab-box tiled, footprint summed in LDS in
  *                   32-bit fixed point (the scale of each box and angle
  *                   bounds every partial sum below 2^31; rounding <= 2^-31

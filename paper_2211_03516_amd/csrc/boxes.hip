@@ -386,6 +386,14 @@ static vam_status build_boxes_into(vam_geometry* h, hipStream_t s) {
   h->n_boxes = (int)ids.size();
   h->n_segments = total;
   {
+    // the most samples of one pixel over all its rays (bounds the
+    // fixed-point forward's sums)
+    const int npix = D.n_u * D.n_v;
+    std::vector<int64_t> per(npix, 0);
+    for (int64_t i = 0; i < total; ++i) per[hs[i].x % npix] += hs[i].z;
+    h->pix_samples_max = per.empty() ? 0 : *std::max_element(per.begin(), per.end());
+  }
+  {
     vam_status st = support_bound(h, G, s);
     if (st != VAM_OK) {
       release();
@@ -609,8 +617,40 @@ __device__ inline float coord(float k, float d, float p, float h) {
 // partials of its rays in a fixed order (pupil index, then rank), so the
 // result does not depend on scheduling.
 
-template <int SY, int SZ, bool CLAMP>
-__device__ inline float march_forward(const float* sv, const SegPos& g, float hx, float hy, float hz,
+// Storage of the staged volume footprint: FP32 values, or (for BF16 and FP16
+// volumes) one 32-bit word per cell holding the 16-bit values of voxel x
+// (low half) and voxel x + 1 (high half), so that a sample reads its 8
+// corners as 4 words instead of 8.  Widening a BF16 or FP16 value to FP32 is
+// exact, so both layouts give the same sums.
+enum { kVolF32 = 0, kVolBF16Pairs = 1, kVolF16Pairs = 2 };
+
+// The x-lerp of the corner pair at word o: v_x + fx (v_{x+1} - v_x), FP32.
+// FP16 halves feed the mixed-precision FMA directly (v_fma_mix_f32 widens
+// either half of its operands), so the pair costs the same two VALU ops as
+// two FP32 values; BF16 halves are widened by a shift and a mask.
+template <int FMT>
+__device__ inline float lerp_x(const uint32_t* sv, unsigned o, float fx) {
+  if constexpr (FMT == kVolF32) {
+    const float lo = __uint_as_float(sv[o]), hi = __uint_as_float(sv[o + 1]);
+    return fmaf(fx, hi - lo, lo);
+  } else if constexpr (FMT == kVolBF16Pairs) {
+    const uint32_t w = sv[o];
+    const float lo = __uint_as_float(w << 16), hi = __uint_as_float(w & 0xffff0000u);
+    return fmaf(fx, hi - lo, lo);
+  } else {
+    const uint32_t w = sv[o];
+    // d = hi - lo straight from the two halves (exact to one FP32 rounding,
+    // as a subtraction of the widened values); the compiler folds the
+    // product by one and would widen both halves separately first.
+    float d;
+    asm("v_fma_mix_f32 %0, %1, 1.0, -%1 op_sel:[1,0,0] op_sel_hi:[1,0,1]" : "=v"(d) : "v"(w));
+    const float lo = (float)__builtin_bit_cast(_Float16, (unsigned short)(w & 0xffffu));
+    return fmaf(fx, d, lo);
+  }
+}
+
+template <int SY, int SZ, bool CLAMP, int FMT>
+__device__ inline float march_forward(const uint32_t* sv, const SegPos& g, float hx, float hy, float hz,
                                       float r_hi, float r_lo) {
   float S = 0.0f;
   for (float kf = g.k1; kf >= g.k0; kf -= 1.0f) {
@@ -619,14 +659,10 @@ __device__ inline float march_forward(const float* sv, const SegPos& g, float hx
     const float z = coord<CLAMP>(kf, g.dz, g.pz, hz);
     const float fx = __builtin_amdgcn_fractf(x), fy = __builtin_amdgcn_fractf(y), fz = __builtin_amdgcn_fractf(z);
     const unsigned o = __umul24((unsigned)z, SZ) + __umul24((unsigned)y, SY) + (unsigned)x;
-    const float* p = sv + o;
-    const float* q = p + SZ;
-    const float v0 = p[0], v1 = p[1], v2 = p[SY], v3 = p[SY + 1];
-    const float v4 = q[0], v5 = q[1], v6 = q[SY], v7 = q[SY + 1];
-    const float c00 = fmaf(fx, v1 - v0, v0);
-    const float c01 = fmaf(fx, v3 - v2, v2);
-    const float c10 = fmaf(fx, v5 - v4, v4);
-    const float c11 = fmaf(fx, v7 - v6, v6);
+    const float c00 = lerp_x<FMT>(sv, o, fx);
+    const float c01 = lerp_x<FMT>(sv, o + SY, fx);
+    const float c10 = lerp_x<FMT>(sv, o + SZ, fx);
+    const float c11 = lerp_x<FMT>(sv, o + SZ + SY, fx);
     const float c0 = fmaf(fy, c01 - c00, c00);
     const float c1 = fmaf(fy, c11 - c10, c10);
     const float val = fmaf(fz, c1 - c0, c0);
@@ -635,18 +671,41 @@ __device__ inline float march_forward(const float* sv, const SegPos& g, float hx
   return S;
 }
 
-template <int B>
-__global__ __launch_bounds__(256) void k_forward_box(MarchParams P, BoxParams Bp, const float* __restrict__ vol,
-                                                     float* __restrict__ part, int64_t slots) {
+// Fixed-point forward (variant 2).  A pixel's value is a sum of segment
+// partials pw.w S, each at most (step / n_pupil) n V in magnitude (sample
+// weights <= step / n_pupil, attenuation <= 1, trilinear values <= V, the
+// volume's largest |value|, n the segment's samples), so the pixel's exact
+// sum and every partial sum of it are at most bound = (step / n_pupil)
+// pix_samples_max V.  With the power of two scale 2^(61 - e), bound < 2^e,
+// every FP32 partial times the scale is exact in FP64 and below 2^61; it is
+// rounded to an integer (<= 1/2 off, i.e. <= bound 2^-62) and added to the
+// pixel's 64-bit integer, which stays below 2^62: integer adds commute, so
+// the result does not depend on the order of the atomics.
+__device__ inline double fx_scale(unsigned vmax_bits, double coef) {
+  const double bound = (double)__uint_as_float(vmax_bits) * coef;
+  if (!(bound > 0.0)) return 1.0;  // all partials are zero
+  int e;
+  (void)frexp(bound, &e);           // bound < 2^e
+  return ldexp(1.0, 61 - e);
+}
+
+// vol: the padded working volume, FP32 values or 16-bit pairs (FMT).
+// FX = false: partial sums to part[angle][rank][ray] (slots per angle);
+// FX = true: fixed-point adds into pfx[angle][pixel].
+template <int B, int FMT, bool FX>
+__global__ __launch_bounds__(256) void k_forward_box(MarchParams P, BoxParams Bp, const uint32_t* __restrict__ vol,
+                                                     float* __restrict__ part, int64_t slots,
+                                                     unsigned long long* __restrict__ pfx,
+                                                     const unsigned* __restrict__ vmax, double fx_coef) {
   constexpr int SY = Fixed<B>::WXY, SZ = SY * SY, NC = SZ * Fixed<B>::WZ;
-  __shared__ float sv[NC];
+  __shared__ uint32_t sv[NC];
   int b, a;
   if (!work_item(Bp.nboxes, Bp.na, Bp.xcd, b, a)) return;
   const double2 cs = P.cs[P.a0 + a];
   const Foot f = footprint(Bp, Bp.box_id[b], cs.x, cs.y, P.cx, P.cy);
   for (int i = threadIdx.x; i < NC; i += blockDim.x) {
     const int z = i / SZ, rem = i - z * SZ, y = rem / SY, x = rem - y * SY;
-    float v = 0.0f;
+    uint32_t v = 0u;
     if (x < f.WX && y < f.WY && z < f.WZ)
       v = vol[((int64_t)(f.Z0 + z) * Bp.py + (f.Y0 + y)) * Bp.px + (f.X0 + x)];
     sv[i] = v;
@@ -656,13 +715,61 @@ __global__ __launch_bounds__(256) void k_forward_box(MarchParams P, BoxParams Bp
   const float c = (float)cs.x, s = (float)cs.y, sc = P.step * c, ss = P.step * s;
   const int s_end = Bp.box_begin[b + 1];
   float* out = part + (int64_t)a * slots;
+  double scale = 1.0;
+  bool finite = true;
+  if constexpr (FX) {
+    const unsigned vm = *vmax;
+    finite = vm < 0x7f800000u;
+    scale = fx_scale(vm, fx_coef);
+  }
+  unsigned long long* row = pfx + (int64_t)a * Bp.npix;
   for (int si = Bp.box_begin[b] + threadIdx.x; si < s_end; si += blockDim.x) {
     const float4 pw = Bp.seg.pw[si], dn = Bp.seg.dn[si];
     const SegPos g = seg_pos(pw, dn, __float_as_int(dn.w), f, c, s, sc, ss, P.step);
-    const float S = seg_inside(g, hx, hy, hz) ? march_forward<SY, SZ, false>(sv, g, hx, hy, hz, P.r_hi, P.r_lo)
-                                              : march_forward<SY, SZ, true>(sv, g, hx, hy, hz, P.r_hi, P.r_lo);
-    out[Bp.seg.idx[si]] = pw.w * S;
+    const float S = seg_inside(g, hx, hy, hz) ? march_forward<SY, SZ, false, FMT>(sv, g, hx, hy, hz, P.r_hi, P.r_lo)
+                                              : march_forward<SY, SZ, true, FMT>(sv, g, hx, hy, hz, P.r_hi, P.r_lo);
+    const float v = pw.w * S;
+    if constexpr (FX) {
+      // the slot rank * n_rays + pupil * npix + pixel, modulo npix, is the pixel
+      if (finite && v != 0.0f)
+        atomicAdd(row + (unsigned)Bp.seg.idx[si] % (unsigned)Bp.npix,
+                  (unsigned long long)__double2ll_rn((double)v * scale));
+    } else {
+      out[Bp.seg.idx[si]] = v;
+    }
   }
+}
+
+// Clears the fixed-point projections of a call and the volume maximum.
+__global__ void k_fx_clear(unsigned long long* __restrict__ p, int64_t n, unsigned* __restrict__ vmax) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0ull;
+  if (i == 0) *vmax = 0u;
+}
+
+// Largest |value| of the padded working volume as FP32 bits (non-negative
+// floats order as their bit patterns; a NaN or infinity compares above every
+// finite value).
+template <int FMT>
+__device__ inline unsigned abs_bits(uint32_t w) {
+  if constexpr (FMT == kVolF32) {
+    return w & 0x7fffffffu;
+  } else if constexpr (FMT == kVolBF16Pairs) {
+    return max((w << 16) & 0x7fffffffu, w & 0x7fff0000u);
+  } else {
+    const float lo = (float)__builtin_bit_cast(_Float16, (unsigned short)(w & 0xffffu));
+    const float hi = (float)__builtin_bit_cast(_Float16, (unsigned short)(w >> 16));
+    return max(__float_as_uint(lo) & 0x7fffffffu, __float_as_uint(hi) & 0x7fffffffu);
+  }
+}
+
+template <int FMT>
+__global__ __launch_bounds__(256) void k_absmax(const uint32_t* __restrict__ v, int64_t n, unsigned* __restrict__ vmax) {
+  unsigned m = 0u;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    m = max(m, abs_bits<FMT>(v[i]));
+  for (int off = 32; off > 0; off >>= 1) m = max(m, (unsigned)__shfl_xor((int)m, off));
+  if ((threadIdx.x & 63) == 0) atomicMax(vmax, m);
 }
 
 template <typename PT>
@@ -684,6 +791,20 @@ __device__ inline void store_proj<uint16_t>(uint16_t* p, int64_t i, float x) {
 template <>
 __device__ inline void store_proj<__half>(__half* p, int64_t i, float x) {
   p[i] = __float2half_rn(x);
+}
+
+// Fixed-point projections -> stored projections: the integer over the scale,
+// rounded to FP32 (then to BF16 / FP16 on store); all NaN if the volume held
+// a NaN or an infinity.
+template <typename PT>
+__global__ void k_fx_store(const unsigned long long* __restrict__ pfx, PT* __restrict__ proj, int64_t n,
+                           const unsigned* __restrict__ vmax, double fx_coef) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const unsigned vm = *vmax;
+  const bool finite = vm < 0x7f800000u;
+  const float x = finite ? (float)((double)(long long)pfx[i] / fx_scale(vm, fx_coef)) : __uint_as_float(0x7fc00000u);
+  store_proj(proj, i, x);
 }
 
 template <typename PT>
@@ -716,14 +837,102 @@ __global__ void k_reduce_segments(const float* __restrict__ part, const int* __r
   store_proj(proj, i, acc);
 }
 
-template <int B>
-static void launch_forward_box(dim3 grid, hipStream_t s, const MarchParams& P, const BoxParams& Bp,
-                               const float* vol, float* part, int64_t slots) {
-  hipLaunchKernelGGL((k_forward_box<B>), grid, dim3(256), 0, s, P, Bp, vol, part, slots);
+// Forward launch arguments beyond the march and box parameters.
+struct FwdOut {
+  float* part;              // partial sums (fx = false)
+  int64_t slots;
+  unsigned long long* pfx;  // fixed-point projections (fx = true)
+  const unsigned* vmax;
+  double fx_coef;
+};
+
+template <int B, int FMT, bool FX>
+static void launch_forward_box_f(dim3 grid, hipStream_t s, const MarchParams& P, const BoxParams& Bp,
+                                 const uint32_t* vol, const FwdOut& o) {
+  hipLaunchKernelGGL((k_forward_box<B, FMT, FX>), grid, dim3(256), 0, s, P, Bp, vol, o.part, o.slots, o.pfx, o.vmax,
+                     o.fx_coef);
+}
+
+template <int B, bool FX>
+static void launch_forward_box(dim3 grid, hipStream_t s, const MarchParams& P, const BoxParams& Bp, int fmt,
+                               const uint32_t* vol, const FwdOut& o) {
+  switch (fmt) {
+    case kVolBF16Pairs: launch_forward_box_f<B, kVolBF16Pairs, FX>(grid, s, P, Bp, vol, o); break;
+    case kVolF16Pairs: launch_forward_box_f<B, kVolF16Pairs, FX>(grid, s, P, Bp, vol, o); break;
+    default: launch_forward_box_f<B, kVolF32, FX>(grid, s, P, Bp, vol, o); break;
+  }
+}
+
+template <bool FX>
+static void launch_forward_box_edge(int edge, dim3 grid, hipStream_t s, const MarchParams& P, const BoxParams& Bp,
+                                    int fmt, const uint32_t* vol, const FwdOut& o) {
+  switch (edge) {
+    case 8: launch_forward_box<8, FX>(grid, s, P, Bp, fmt, vol, o); break;
+    case 12: launch_forward_box<12, FX>(grid, s, P, Bp, fmt, vol, o); break;
+    default: launch_forward_box<16, FX>(grid, s, P, Bp, fmt, vol, o); break;
+  }
+}
+
+// Caller volume -> interior of the padded working volume as 16-bit pairs:
+// word (z, y, x) holds voxel x (low half) and voxel x + 1 (high half) of the
+// padded grid, stored as given (zero in the padding).
+__global__ void k_pad_pairs(const uint16_t* __restrict__ vol, uint32_t* __restrict__ vp, int nx, int ny, int nz,
+                            int px, int py, int pz) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)px * py * pz) return;
+  const int x = (int)(i % px), y = (int)((i / px) % py), z = (int)(i / ((int64_t)px * py));
+  const int ix = x - kPad, iy = y - kPad, iz = z - kPad;
+  uint32_t lo = 0u, hi = 0u;
+  if (iy >= 0 && iy < ny && iz >= 0 && iz < nz) {
+    const int64_t row = ((int64_t)iz * ny + iy) * nx;
+    if (ix >= 0 && ix < nx) lo = vol[row + ix];
+    if (ix + 1 >= 0 && ix + 1 < nx) hi = vol[row + ix + 1];
+  }
+  vp[i] = lo | (hi << 16);
+}
+
+// Variant 2: every segment adds its partial to its pixel in 64-bit fixed
+// point (scale from the volume's largest |value|), then one pass rounds the
+// integers to the stored projections.
+template <typename PT>
+static vam_status forward_box_fx(vam_geometry* h, const MarchParams& P, PT* proj, int na, int fmt, hipStream_t s) {
+  const vam_geometry_desc& D = h->desc;
+  const int64_t npix = (int64_t)D.n_u * D.n_v;
+  if (!h->proj_fx) {
+    VAM_HIP_TRY(dev_alloc((void**)&h->proj_fx, (int64_t)D.n_angles * npix * sizeof(int64_t)),
+                "allocating the fixed-point projections");
+  }
+  if (!h->vol_absmax) VAM_HIP_TRY(dev_alloc((void**)&h->vol_absmax, sizeof(unsigned)), "allocating a maximum");
+  unsigned long long* pfx = (unsigned long long*)h->proj_fx;
+  const int64_t n = (int64_t)na * npix;
+  hipLaunchKernelGGL(k_fx_clear, dim3((unsigned)std::max<int64_t>((n + 255) / 256, 1)), dim3(256), 0, s, pfx, n,
+                     h->vol_absmax);
+  const uint32_t* vol = (const uint32_t*)h->vol_pad;
+  const unsigned mb = (unsigned)std::min<int64_t>((h->pad_voxels + 255) / 256, 2048);
+  switch (fmt) {
+    case kVolBF16Pairs:
+      hipLaunchKernelGGL(k_absmax<kVolBF16Pairs>, dim3(mb), dim3(256), 0, s, vol, h->pad_voxels, h->vol_absmax);
+      break;
+    case kVolF16Pairs:
+      hipLaunchKernelGGL(k_absmax<kVolF16Pairs>, dim3(mb), dim3(256), 0, s, vol, h->pad_voxels, h->vol_absmax);
+      break;
+    default: hipLaunchKernelGGL(k_absmax<kVolF32>, dim3(mb), dim3(256), 0, s, vol, h->pad_voxels, h->vol_absmax);
+  }
+  const double coef = D.step / D.n_pupil * (double)h->pix_samples_max;
+  if (h->n_boxes > 0) {
+    const BoxParams Bp = box_params(h, h->seg_fwd, na, h->xcd_forward);
+    const FwdOut o{nullptr, 0, pfx, h->vol_absmax, coef};
+    launch_forward_box_edge<true>(h->boxes.B, work_grid(h->n_boxes, na, Bp.xcd), s, P, Bp, fmt, vol, o);
+  }
+  hipLaunchKernelGGL(k_fx_store<PT>, dim3((unsigned)std::max<int64_t>((n + 255) / 256, 1)), dim3(256), 0, s, pfx,
+                     proj, n, h->vol_absmax, coef);
+  VAM_HIP_TRY(hipGetLastError(), "launching the fixed-point forward projector");
+  return VAM_OK;
 }
 
 template <typename PT>
-static vam_status forward_box_t(vam_geometry* h, const MarchParams& P0, PT* proj, int na, hipStream_t s) {
+static vam_status forward_box_t(vam_geometry* h, const MarchParams& P0, PT* proj, int na, int fmt, hipStream_t s) {
+  if (h->forward_variant == 2) return forward_box_fx(h, P0, proj, na, fmt, s);
   const vam_geometry_desc& D = h->desc;
   const int64_t slots = (int64_t)std::max(h->max_seg_per_ray, 1) * h->n_rays;
   if (!h->seg_part) {
@@ -748,12 +957,9 @@ static vam_status forward_box_t(vam_geometry* h, const MarchParams& P0, PT* proj
     P.a0 = P0.a0 + c0;
     if (h->n_boxes > 0) {
       const BoxParams Bp = box_params(h, h->seg_fwd, nc, h->xcd_forward);
-      const dim3 grid = work_grid(h->n_boxes, nc, Bp.xcd);
-      switch (h->boxes.B) {
-        case 8: launch_forward_box<8>(grid, s, P, Bp, h->vol_pad, h->seg_part, slots); break;
-        case 12: launch_forward_box<12>(grid, s, P, Bp, h->vol_pad, h->seg_part, slots); break;
-        default: launch_forward_box<16>(grid, s, P, Bp, h->vol_pad, h->seg_part, slots); break;
-      }
+      const FwdOut o{h->seg_part, slots, nullptr, nullptr, 0.0};
+      launch_forward_box_edge<false>(h->boxes.B, work_grid(h->n_boxes, nc, Bp.xcd), s, P, Bp, fmt,
+                                     (const uint32_t*)h->vol_pad, o);
     }
     const int64_t n = (int64_t)nc * npix;
     hipLaunchKernelGGL(k_reduce_segments<PT>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, h->seg_part,
@@ -763,15 +969,24 @@ static vam_status forward_box_t(vam_geometry* h, const MarchParams& P0, PT* proj
   return VAM_OK;
 }
 
-vam_status launch_box_forward(vam_geometry* h, const MarchParams& P, void* proj, vam_dtype proj_t, int na,
-                              hipStream_t s) {
+// The padded working volume for the box forward: FP32 values (from an FP32
+// caller volume) or 16-bit pairs (from a BF16 or FP16 one), in h->vol_pad.
+void pad_box_volume(vam_geometry* h, const void* vol, vam_dtype vol_t, hipStream_t s) {
+  const vam_geometry_desc& D = h->desc;
+  hipLaunchKernelGGL(k_pad_pairs, dim3((unsigned)((h->pad_voxels + 255) / 256)), dim3(256), 0, s,
+                     (const uint16_t*)vol, (uint32_t*)h->vol_pad, D.nx, D.ny, D.nz, h->px, h->py, h->pz);
+}
+
+vam_status launch_box_forward(vam_geometry* h, const MarchParams& P, void* proj, vam_dtype proj_t, vam_dtype vol_t,
+                              int na, hipStream_t s) {
   if (!h->boxes_ready)
     return fail(VAM_ERR_INVALID_ARG, "the box decomposition is not available (a rebuild failed); "
                                      "set the box edge again or create a new geometry");
+  const int fmt = vol_t == VAM_BF16 ? kVolBF16Pairs : vol_t == VAM_F16 ? kVolF16Pairs : kVolF32;
   switch (proj_t) {
-    case VAM_F32: return forward_box_t(h, P, (float*)proj, na, s);
-    case VAM_BF16: return forward_box_t(h, P, (uint16_t*)proj, na, s);
-    case VAM_F16: return forward_box_t(h, P, (__half*)proj, na, s);
+    case VAM_F32: return forward_box_t(h, P, (float*)proj, na, fmt, s);
+    case VAM_BF16: return forward_box_t(h, P, (uint16_t*)proj, na, fmt, s);
+    case VAM_F16: return forward_box_t(h, P, (__half*)proj, na, fmt, s);
   }
   return fail(VAM_ERR_INVALID_ARG, "unknown projection dtype");
 }

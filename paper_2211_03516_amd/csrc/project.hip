@@ -236,17 +236,18 @@ __global__ __launch_bounds__(256) void k_back2(MarchParams P, const PT* __restri
   }
 }
 
-// Caller volume -> interior of the padded FP32 working volume.
+// Caller volume -> the padded FP32 working volume, padding included (zero),
+// so that no earlier call's contents (16-bit pairs of the box forward) stay
+// behind in it.
 template <typename VT>
-__global__ void k_pad(const VT* __restrict__ vol, float* __restrict__ vp, int nx, int ny, int nz,
-                      int px, int py) {
+__global__ void k_pad(const VT* __restrict__ vol, float* __restrict__ vp, int nx, int ny, int nz, int px, int py,
+                      int pz) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t n = (int64_t)nx * ny * nz;
-  if (i >= n) return;
-  const int x = (int)(i % nx);
-  const int y = (int)((i / nx) % ny);
-  const int z = (int)(i / ((int64_t)nx * ny));
-  vp[((int64_t)(z + kPad) * py + (y + kPad)) * px + (x + kPad)] = load_elem(vol, i);
+  if (i >= (int64_t)px * py * pz) return;
+  const int x = (int)(i % px) - kPad, y = (int)((i / px) % py) - kPad, z = (int)(i / ((int64_t)px * py)) - kPad;
+  float v = 0.0f;
+  if (x >= 0 && x < nx && y >= 0 && y < ny && z >= 0 && z < nz) v = load_elem(vol, ((int64_t)z * ny + y) * nx + x);
+  vp[i] = v;
 }
 
 // Interior of the padded accumulator -> caller dose (overwrite or add).
@@ -311,27 +312,29 @@ vam_status launch_forward(vam_geometry* h, const void* vol, vam_dtype vol_t, voi
   const vam_geometry_desc& D = h->desc;
   if (h->forward_variant == 1 && !v2_eligible(h))
     return fail(VAM_ERR_UNSUPPORTED, "the ray-driven forward needs a padded volume below 2^28 voxels");
-  const int64_t nvox = (int64_t)D.nx * D.ny * D.nz;
-  const unsigned vb = blocks_for(nvox, 256);
-  switch (vol_t) {
+  const unsigned vb = blocks_for(h->pad_voxels, 256);
+  // the box forward stages a BF16 / FP16 volume as 16-bit pairs
+  const bool pairs = h->forward_variant != 1 && vol_t != VAM_F32;
+  if (pairs) pad_box_volume(h, vol, vol_t, s);
+  else switch (vol_t) {
     case VAM_F32:
       hipLaunchKernelGGL(k_pad<float>, dim3(vb), dim3(256), 0, s, (const float*)vol, h->vol_pad,
-                         D.nx, D.ny, D.nz, h->px, h->py);
+                         D.nx, D.ny, D.nz, h->px, h->py, h->pz);
       break;
     case VAM_BF16:
       hipLaunchKernelGGL(k_pad<uint16_t>, dim3(vb), dim3(256), 0, s, (const uint16_t*)vol, h->vol_pad,
-                         D.nx, D.ny, D.nz, h->px, h->py);
+                         D.nx, D.ny, D.nz, h->px, h->py, h->pz);
       break;
     case VAM_F16:
       hipLaunchKernelGGL(k_pad<__half>, dim3(vb), dim3(256), 0, s, (const __half*)vol, h->vol_pad,
-                         D.nx, D.ny, D.nz, h->px, h->py);
+                         D.nx, D.ny, D.nz, h->px, h->py, h->pz);
       break;
   }
   VAM_HIP_TRY(hipGetLastError(), "launching the volume copy");
   MarchParams P = march_params(h, a0);
   VAM_HIP_TRY(hipEventRecord(h->ev[0], s), "recording an event");
-  if (h->forward_variant == 0) {
-    vam_status st = launch_box_forward(h, P, proj, proj_t, na, s);
+  if (h->forward_variant != 1) {
+    vam_status st = launch_box_forward(h, P, proj, proj_t, vol_t, na, s);
     if (st != VAM_OK) return st;
   } else {
     dim3 grid((D.n_u + 63) / 64, (D.n_v + 3) / 4, na), block(64, 4);

@@ -336,7 +336,7 @@ static void free_handle(vam_geometry* h) {
   free_boxes(h);
   free_gather(h);
   void* ptrs[] = {h->rays, h->ray64, h->angle_cs, h->vol_pad, h->dose_pad64,
-                  h->resid, h->grad, h->dose_tmp, h->loss_part};
+                  h->resid, h->grad, h->dose_tmp, h->loss_part, h->proj_fx, h->vol_absmax};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   h->magic = 0;
@@ -415,8 +415,6 @@ vam_status vam_setup_geometry(const vam_geometry_desc* desc, hipStream_t stream,
                            hipMemcpyHostToDevice, stream), "copying the pupil table");
   SETUP_TRY(hipMemcpyAsync(h->angle_cs, cs.data(), cs.size() * sizeof(double2),
                            hipMemcpyHostToDevice, stream), "copying angles");
-  // the padding of the working volume stays zero for the handle's lifetime
-  SETUP_TRY(hipMemsetAsync(h->vol_pad, 0, h->pad_voxels * sizeof(float), stream), "clearing the volume");
   SETUP_TRY(hipMemsetAsync(count_dev, 0, sizeof(unsigned long long), stream), "clearing a counter");
 
   TraceParams P = make_params(h, desc->pupil_xy ? pupil_dev : nullptr);
@@ -489,7 +487,7 @@ vam_status vam_set_variant(vam_geometry_t h, int32_t op, int32_t variant) {
   clear_error();
   if (!valid_handle(h)) return fail(VAM_ERR_BAD_HANDLE, "not a live geometry handle");
   if (op == 0) {
-    if (variant < 0 || variant > 1) return fail(VAM_ERR_INVALID_ARG, "unknown forward variant %d", variant);
+    if (variant < 0 || variant > 2) return fail(VAM_ERR_INVALID_ARG, "unknown forward variant %d", variant);
     h->forward_variant = variant;
   } else if (op == 1) {
     if (variant < 0 || variant > 2) return fail(VAM_ERR_INVALID_ARG, "unknown deposit variant %d", variant);

@@ -120,6 +120,12 @@ struct vam_geometry {
   int max_seg_per_ray;
   float* seg_part;               // forward partial sums [angle][rank][ray], on first use
   int seg_part_angles;           // angles per chunk of seg_part
+  // fixed-point forward (variant 2): projections as 64-bit integers
+  // [n_angles][n_v][n_u] and the volume's largest |value| (FP32 bits), on
+  // first use; the most samples of one pixel (all its rays), set at build
+  int64_t* proj_fx;
+  unsigned* vol_absmax;
+  int64_t pix_samples_max;
   int* box_begin;                // [n_boxes + 1] segment offsets
   int* box_id;                   // [n_boxes] linear box index (x fastest)
   int* box_supp;                 // [n_boxes] most samples of the box in any 4 x 4 x 3 block of lab unit cells
@@ -160,8 +166,10 @@ MarchParams march_params(const vam_geometry* h, int a0);
 // rebuilds from scratch and leaves boxes_ready = 0 (and nothing allocated)
 // on failure
 vam_status build_boxes(vam_geometry* h, hipStream_t s);
-vam_status launch_box_forward(vam_geometry* h, const MarchParams& P, void* proj, vam_dtype proj_t, int na,
-                              hipStream_t s);
+vam_status launch_box_forward(vam_geometry* h, const MarchParams& P, void* proj, vam_dtype proj_t, vam_dtype vol_t,
+                              int na, hipStream_t s);
+// the box forward's padded working volume from a BF16 or FP16 volume
+void pad_box_volume(vam_geometry* h, const void* vol, vam_dtype vol_t, hipStream_t s);
 vam_status launch_box_deposit(vam_geometry* h, const MarchParams& P, const void* proj, vam_dtype proj_t,
                               int na, double* acc, hipStream_t s);
 void free_boxes(vam_geometry* h);

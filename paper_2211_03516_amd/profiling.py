@@ -79,7 +79,8 @@ def traffic(fetch_csv, write_csv, copy_mib, root, calls=None, sq_csv=None, l2_cs
     scaled by what they read for the largest copy kernel (a device copy of
     copy_mib MiB: reads and writes exactly that much).  `calls` maps each
     kernel to the number of operator passes in the profiled run.  With
-    sq_csv, also the VALU wave-instructions per call (SQ_INSTS_VALU); with
+    sq_csv, also the VALU wave-instructions (SQ_INSTS_VALU), VALU thread
+    cycles, LDS instructions and LDS bank-conflict cycles per call; with
     l2_csv (a run with the same copy), the L1 -> L2 read and write bytes per
     call (TCP_TCC_READ_REQ_sum / TCP_TCC_WRITE_REQ_sum times the copy's
     bytes per request)."""
@@ -108,10 +109,15 @@ def traffic(fetch_csv, write_csv, copy_mib, root, calls=None, sq_csv=None, l2_cs
             w = sum(write[name]) / c * fw * 1024
             out[name] = {"fetch_bytes": f, "write_bytes": w, "dispatches_per_call": len(fetch[name]) / c}
     if sq_csv:
-        per, _ = _sums(sq_csv, {"SQ_INSTS_VALU"})
+        per, _ = _sums(sq_csv, {"SQ_INSTS_VALU", "SQ_THREAD_CYCLES_VALU", "SQ_INSTS_LDS", "SQ_LDS_BANK_CONFLICT"})
         for name in KERNELS:
             if name in out and "SQ_INSTS_VALU" in per[name]:
-                out[name]["valu_insts"] = per[name]["SQ_INSTS_VALU"][0] / calls.get(name, 1)
+                c = calls.get(name, 1)
+                out[name]["valu_insts"] = per[name]["SQ_INSTS_VALU"][0] / c
+                for key, counter in (("valu_thread_cycles", "SQ_THREAD_CYCLES_VALU"), ("lds_insts", "SQ_INSTS_LDS"),
+                                     ("lds_bank_conflict_cycles", "SQ_LDS_BANK_CONFLICT")):
+                    if counter in per[name]:
+                        out[name][key] = per[name][counter][0] / c
     if l2_csv:
         per, copy = _sums(l2_csv, {"TCP_TCC_READ_REQ_sum", "TCP_TCC_WRITE_REQ_sum"})
         nbytes = copy_mib * 1048576.0

@@ -355,14 +355,47 @@ def test_forward_variants_agree():
     rng = synth.SplitMix64(11)
     x = rng.uniform(48 ** 3).reshape(48, 48, 48)
     ref = oracle.forward(oracle.Geometry(p), x)
-    for variant in (vam.FWD_RAY, vam.FWD_DEFAULT):
+    for variant in (vam.FWD_RAY, vam.FWD_DEFAULT, vam.FWD_FIXED):
         g.set_forward_variant(variant)
         P1 = g.forward(to_dev(x))
         P2 = g.forward(to_dev(x))
         assert torch.equal(P1, P2)              # every variant is deterministic
         check(P1.cpu().numpy(), ref, what="forward variant %d" % variant)
     with pytest.raises(vam.VamError):
-        g.set_forward_variant(2)
+        g.set_forward_variant(3)
+    g.close()
+
+
+def test_fixed_point_forward():
+    """Forward variant 2 adds each segment's partial to its pixel as a 64-bit
+    integer: a signed volume at every box edge and in BF16 / FP16, a zero
+    volume, an exact power-of-two rescaling (the scale is a power of two, so
+    the integers do not change), and a NaN (every value NaN)."""
+    n = 44
+    p = c2_small(n, n_pupil=4, n_angles=7)
+    g = gpu_geom(p)
+    og = oracle.Geometry(p)
+    g.set_forward_variant(vam.FWD_FIXED)
+    rng = synth.SplitMix64(23)
+    x = rng.uniform(n ** 3).reshape(n, n, n) - 0.4
+    ref = oracle.forward(og, x)
+    for edge in (8, 16, 12):
+        g.set_box_edge(edge)
+        check(g.forward(to_dev(x)).cpu().numpy(), ref, what="fixed-point forward, edge %d, signed" % edge)
+    P = g.forward(to_dev(x))
+    P_big = g.forward(to_dev(x) * 2.0 ** 40)
+    P_small = g.forward(to_dev(x) * 2.0 ** -40)
+    assert torch.equal(P_big, P * 2.0 ** 40) and torch.equal(P_small, P * 2.0 ** -40)
+    for dt, tdt in (("bf16", torch.bfloat16), ("f16", torch.float16)):
+        xs = torch.from_numpy(x).to(tdt)
+        check(g.forward(xs.to(DEV)).cpu().numpy(), oracle.forward(og, xs.double().numpy()),
+              what="fixed-point forward, %s pairs" % dt)
+    assert torch.count_nonzero(g.forward(torch.zeros(n, n, n, device=DEV))) == 0
+    bad = to_dev(x)
+    bad[20, 3, 7] = float("nan")
+    assert torch.isnan(g.forward(bad)).all()
+    # the fixed-point sums are not affected by the previous call's NaN
+    check(g.forward(to_dev(x)).cpu().numpy(), ref, what="fixed-point forward after a NaN")
     g.close()
 
 
@@ -592,6 +625,28 @@ def test_reduced_precision_storage(dt, bound):
     g.close()
 
 
+def test_forward_dtypes_in_turn_on_one_handle():
+    # the box forward stages BF16 / FP16 volumes as 16-bit pairs and FP32
+    # volumes as values in the same working buffer: every call must replace
+    # all of it, padding included, whatever the previous call's format
+    p = c2_small(40, n_pupil=4, n_angles=6)
+    g = gpu_geom(p)
+    og = oracle.Geometry(p)
+    rng = synth.SplitMix64(19)
+    x = rng.uniform(40 ** 3).reshape(40, 40, 40)
+    ref = oracle.forward(og, x)
+    for dt in ("bf16", "f32", "f16", "f32", "f16", "bf16"):
+        tdt = {"f32": torch.float32, "bf16": torch.bfloat16, "f16": torch.float16}[dt]
+        xs = torch.from_numpy(x).to(tdt)
+        P = g.forward(xs.to(DEV)).cpu().numpy()
+        if dt == "f32":
+            check(P, ref, what="fp32 after a 16-bit call")
+        else:
+            # against the oracle of the volume as stored: only FP32 sums
+            check(P, oracle.forward(og, xs.double().numpy()), what="%s pairs" % dt)
+    g.close()
+
+
 # ------------------------------------------- full c2 size, sampled outputs --
 
 @pytest.fixture(scope="module")
@@ -603,10 +658,10 @@ def c2_full():
     g.close()
 
 
-@pytest.mark.parametrize("variant", ["default", "ray"])
+@pytest.mark.parametrize("variant", ["default", "ray", "fixed"])
 def test_c2_full_forward_sampled(c2_full, variant):
     p, t, g = c2_full
-    g.set_forward_variant(vam.FWD_RAY if variant == "ray" else vam.FWD_DEFAULT)
+    g.set_forward_variant({"ray": vam.FWD_RAY, "fixed": vam.FWD_FIXED}.get(variant, vam.FWD_DEFAULT))
     say("c2 full forward, 360 angles, variant", variant)
     P = g.forward(to_dev(t)).cpu().numpy()
     g.set_forward_variant(vam.FWD_DEFAULT)
@@ -618,6 +673,17 @@ def test_c2_full_forward_sampled(c2_full, variant):
     ref = oracle.forward_pixels(oracle.Geometry(p), t, ang, vv, uu)
     got = P[ang, vv, uu]
     check(got, ref, what="c2 sampled forward (%d pixels)" % len(ang))
+
+
+def test_c2_full_forward_full_projections(c2_full):
+    # four full 256^2 projections of the benchmark's forward (all 360 angles
+    # computed in one call), angles spread over the turn, pixel by pixel
+    p, t, g = c2_full
+    say("c2 full forward, full projections")
+    P = g.forward(to_dev(t)).cpu().numpy()
+    og = oracle.Geometry(p)
+    for a in (0, 97, 199, 301):
+        check(P[a], oracle.forward(og, t, a0=a, na=1)[0], what="c2 forward angle %d" % a)
 
 
 def test_c2_full_samples_per_pass_8_angles():
