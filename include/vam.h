@@ -114,9 +114,14 @@ vam_status vam_destroy_geometry(vam_geometry_t h);
  * writes proj[a - angle_begin][v][u] for angles angle_begin ..
  * angle_begin+angle_count-1 from vol[nz][ny][nx].  vol_t and proj_t select
  * the element types.  Deterministic: the same inputs give the same bits.
+ * Each pixel's segment sums are added in 64-bit fixed point (rounding
+ * <= 2^-62 of a bound per add, see vam_set_variant, op 0) and the total is
+ * rounded once; a NaN or infinity anywhere in the volume makes every
+ * projection value of the call NaN.  The first call allocates
+ * n_angles x n_u x n_v x 8 bytes in the handle.
  * Errors: VAM_ERR_BAD_HANDLE; VAM_ERR_INVALID_ARG for NULL pointers, bad
  * dtypes, angle_count < 1 or an angle range outside [0, n_angles);
- * VAM_ERR_HIP. */
+ * VAM_ERR_OUT_OF_MEMORY; VAM_ERR_HIP. */
 vam_status vam_forward_project(vam_geometry_t h, const void* vol, vam_dtype vol_t,
                                void* proj, vam_dtype proj_t,
                                int32_t angle_begin, int32_t angle_count,
@@ -171,7 +176,8 @@ vam_status vam_back_project_noalloc(vam_geometry_t h, const void* proj, vam_dtyp
  * receives d; the loss is reduced in FP64.  loss_out (optional) receives the
  * loss of the projections BEFORE the update; passing it synchronises
  * `stream`.  The first call allocates the step's buffers (two volumes and
- * an FP32 gradient of the projections' shape) in the handle.  Errors:
+ * an FP32 gradient of the projections' shape, and the forward
+ * projection's) in the handle.  Errors:
  * VAM_ERR_BAD_HANDLE; VAM_ERR_INVALID_ARG for NULL pointers, an unknown
  * dtype or parameters outside the ranges below; VAM_ERR_OUT_OF_MEMORY;
  * VAM_ERR_HIP. */
@@ -231,16 +237,18 @@ vam_status vam_export_rays(vam_geometry_t h, double* out);
 /* Select the kernel variant of an operator for this handle (measurement
  * and testing; every variant computes the same operator).
  *   op 0, forward:  0 = default: lab-box tiled, volume footprint staged in
- *                   LDS, deterministic per-segment partial sums;
+ *                   LDS, each segment's partial added to its pixel as a
+ *                   64-bit integer (scale: a power of two from the volume's
+ *                   largest |value| and the most samples of a pixel;
+ *                   rounding <= 2^-62 of that bound per add; integer adds
+ *                   make it deterministic); a NaN or infinity anywhere in
+ *                   the volume makes every projection value NaN.  Needs
+ *                   n_angles x n_u x n_v x 8 bytes, allocated on first use;
  *                   1 = ray-driven reference (one lane per pixel and angle,
  *                   buffer gathers from the padded volume);
- *                   2 = lab-box tiled, each segment's partial added to its
- *                   pixel as a 64-bit integer (scale: a power of two from
- *                   the volume's largest |value| and the most samples of a
- *                   pixel; rounding <= 2^-62 of that bound per add; integer
- *                   adds make it deterministic); a NaN or infinity anywhere
- *                   in the volume makes every projection value NaN.  Needs
- *                   n_angles x n_u x n_v x 8 bytes, allocated on first use.
+ *                   2 = lab-box tiled, per-segment FP32 partial sums in a
+ *                   buffer of up to 8 GiB (allocated on first use), added
+ *                   per pixel in a fixed order by a second kernel.
  *   op 1, deposit:  0 = default: lab-box tiled, footprint summed in LDS in
  *                   32-bit fixed point (the scale of each box and angle
  *                   bounds every partial sum below 2^31; rounding <= 2^-31

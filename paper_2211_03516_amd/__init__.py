@@ -31,7 +31,7 @@ RAY_FIELDS = 12
 # vam_set_variant operators and variants (include/vam.h)
 OP_FORWARD, OP_DEPOSIT, OP_BOX_EDGE, OP_SEG_ORDER, OP_DEPOSIT_THREADS = 0, 1, 2, 4, 5
 OP_SEG_ORDER_FWD, OP_ANGLE_BLOCK_DEPOSIT, OP_ANGLE_BLOCK_FORWARD = 7, 8, 9
-FWD_DEFAULT, FWD_RAY, FWD_FIXED = 0, 1, 2
+FWD_DEFAULT, FWD_RAY, FWD_PARTIALS = 0, 1, 2
 ADJ_DEFAULT, ADJ_RAY, ADJ_GATHER = 0, 1, 2
 BOX_EDGES = (8, 12, 16)
 

@@ -613,9 +613,10 @@ __device__ inline float coord(float k, float d, float p, float h) {
 // the box gathers its samples from LDS.  The segment's partial sum (Horner
 // over its samples from the far end, S <- S r + val with r = exp(-alpha
 // step) applied as r_hi + r_lo, times the weight of its first sample) is
-// written to part[angle][rank][ray]; a second kernel adds, per pixel, the
-// partials of its rays in a fixed order (pupil index, then rank), so the
-// result does not depend on scheduling.
+// added to its pixel as a 64-bit integer (the default), or written to
+// part[angle][rank][ray] for a second kernel that adds, per pixel, the
+// partials of its rays in a fixed order (pupil index, then rank).  Either
+// way the result does not depend on scheduling.
 
 // Storage of the staged volume footprint: FP32 values, or (for BF16 and FP16
 // volumes) one 32-bit word per cell holding the 16-bit values of voxel x
@@ -671,7 +672,7 @@ __device__ inline float march_forward(const uint32_t* sv, const SegPos& g, float
   return S;
 }
 
-// Fixed-point forward (variant 2).  A pixel's value is a sum of segment
+// Fixed-point forward (the default).  A pixel's value is a sum of segment
 // partials pw.w S, each at most (step / n_pupil) n V in magnitude (sample
 // weights <= step / n_pupil, attenuation <= 1, trilinear values <= V, the
 // volume's largest |value|, n the segment's samples), so the pixel's exact
@@ -891,9 +892,10 @@ __global__ void k_pad_pairs(const uint16_t* __restrict__ vol, uint32_t* __restri
   vp[i] = lo | (hi << 16);
 }
 
-// Variant 2: every segment adds its partial to its pixel in 64-bit fixed
-// point (scale from the volume's largest |value|), then one pass rounds the
-// integers to the stored projections.
+// Default forward: every segment adds its partial to its pixel in 64-bit
+// fixed point (scale from the volume's largest |value|), then one pass
+// rounds the integers to the stored projections.  Variant 2 (below) writes
+// FP32 partial sums instead and adds them per pixel in a fixed order.
 template <typename PT>
 static vam_status forward_box_fx(vam_geometry* h, const MarchParams& P, PT* proj, int na, int fmt, hipStream_t s) {
   const vam_geometry_desc& D = h->desc;
@@ -932,7 +934,7 @@ static vam_status forward_box_fx(vam_geometry* h, const MarchParams& P, PT* proj
 
 template <typename PT>
 static vam_status forward_box_t(vam_geometry* h, const MarchParams& P0, PT* proj, int na, int fmt, hipStream_t s) {
-  if (h->forward_variant == 2) return forward_box_fx(h, P0, proj, na, fmt, s);
+  if (h->forward_variant != 2) return forward_box_fx(h, P0, proj, na, fmt, s);
   const vam_geometry_desc& D = h->desc;
   const int64_t slots = (int64_t)std::max(h->max_seg_per_ray, 1) * h->n_rays;
   if (!h->seg_part) {

@@ -355,7 +355,7 @@ def test_forward_variants_agree():
     rng = synth.SplitMix64(11)
     x = rng.uniform(48 ** 3).reshape(48, 48, 48)
     ref = oracle.forward(oracle.Geometry(p), x)
-    for variant in (vam.FWD_RAY, vam.FWD_DEFAULT, vam.FWD_FIXED):
+    for variant in (vam.FWD_RAY, vam.FWD_PARTIALS, vam.FWD_DEFAULT):
         g.set_forward_variant(variant)
         P1 = g.forward(to_dev(x))
         P2 = g.forward(to_dev(x))
@@ -367,7 +367,7 @@ def test_forward_variants_agree():
 
 
 def test_fixed_point_forward():
-    """Forward variant 2 adds each segment's partial to its pixel as a 64-bit
+    """The default forward adds each segment's partial to its pixel as a 64-bit
     integer: a signed volume at every box edge and in BF16 / FP16, a zero
     volume, an exact power-of-two rescaling (the scale is a power of two, so
     the integers do not change), and a NaN (every value NaN)."""
@@ -375,7 +375,6 @@ def test_fixed_point_forward():
     p = c2_small(n, n_pupil=4, n_angles=7)
     g = gpu_geom(p)
     og = oracle.Geometry(p)
-    g.set_forward_variant(vam.FWD_FIXED)
     rng = synth.SplitMix64(23)
     x = rng.uniform(n ** 3).reshape(n, n, n) - 0.4
     ref = oracle.forward(og, x)
@@ -658,10 +657,10 @@ def c2_full():
     g.close()
 
 
-@pytest.mark.parametrize("variant", ["default", "ray", "fixed"])
+@pytest.mark.parametrize("variant", ["default", "ray", "partials"])
 def test_c2_full_forward_sampled(c2_full, variant):
     p, t, g = c2_full
-    g.set_forward_variant({"ray": vam.FWD_RAY, "fixed": vam.FWD_FIXED}.get(variant, vam.FWD_DEFAULT))
+    g.set_forward_variant({"ray": vam.FWD_RAY, "partials": vam.FWD_PARTIALS}.get(variant, vam.FWD_DEFAULT))
     say("c2 full forward, 360 angles, variant", variant)
     P = g.forward(to_dev(t)).cpu().numpy()
     g.set_forward_variant(vam.FWD_DEFAULT)
