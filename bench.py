@@ -185,6 +185,7 @@ def main():
     ap.add_argument("--seg-order-fwd", type=int, default=-1, help="segment order of the forward")
     ap.add_argument("--deposit-threads", type=int, default=0)
     ap.add_argument("--angle-block", default="", help="deposit[,forward] angle blocks of the XCD-aware work order")
+    ap.add_argument("--forward-lanes", type=int, default=0, help="lanes per segment of the box forward (1 or 2)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
@@ -228,6 +229,8 @@ def main():
         g.set_segment_order(args.seg_order_fwd, forward=True)
     if args.deposit_threads:
         g.set_deposit_threads(args.deposit_threads)
+    if args.forward_lanes:
+        g.set_forward_lanes(args.forward_lanes)
     if args.angle_block:
         ab = [int(v) for v in args.angle_block.split(",")]
         g.set_angle_blocks(deposit=ab[0], forward=ab[1] if len(ab) > 1 else None)

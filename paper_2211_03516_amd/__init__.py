@@ -30,7 +30,7 @@ RAY_FIELDS = 12
 
 # vam_set_variant operators and variants (include/vam.h)
 OP_FORWARD, OP_DEPOSIT, OP_BOX_EDGE, OP_SEG_ORDER, OP_DEPOSIT_THREADS = 0, 1, 2, 4, 5
-OP_SEG_ORDER_FWD, OP_ANGLE_BLOCK_DEPOSIT, OP_ANGLE_BLOCK_FORWARD = 7, 8, 9
+OP_SEG_ORDER_FWD, OP_ANGLE_BLOCK_DEPOSIT, OP_ANGLE_BLOCK_FORWARD, OP_FORWARD_LANES = 7, 8, 9, 10
 FWD_DEFAULT, FWD_RAY, FWD_PARTIALS = 0, 1, 2
 ADJ_DEFAULT, ADJ_RAY, ADJ_GATHER = 0, 1, 2
 BOX_EDGES = (8, 12, 16)
@@ -261,6 +261,11 @@ class Geometry:
         (order 10 with runs of 1024 / 512 / 2048 segments by length) for the
         deposit (or forward)."""
         _check(lib().vam_set_variant(self.handle, OP_SEG_ORDER_FWD if forward else OP_SEG_ORDER, int(order)))
+
+    def set_forward_lanes(self, lanes):
+        """Lanes per segment in the fixed-point box forward: 1, 2, or 0 (the
+        default: 2 for FP32 volumes, 1 for BF16/FP16)."""
+        _check(lib().vam_set_variant(self.handle, OP_FORWARD_LANES, int(lanes)))
 
     def set_angle_blocks(self, deposit=None, forward=None):
         """Work order with the angles of a box in blocks (0: boxes fastest,

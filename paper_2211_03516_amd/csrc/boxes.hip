@@ -650,11 +650,14 @@ __device__ inline float lerp_x(const uint32_t* sv, unsigned o, float fx) {
   }
 }
 
-template <int SY, int SZ, bool CLAMP, int FMT>
-__device__ inline float march_forward(const uint32_t* sv, const SegPos& g, float hx, float hy, float hz,
-                                      float r_hi, float r_lo) {
+// Horner sum over the samples kfirst, kfirst + STRIDE, ..., klast of a
+// segment, from the far end: S <- S r + val with r = r_hi + r_lo the
+// attenuation over STRIDE samples.
+template <int SY, int SZ, bool CLAMP, int FMT, int STRIDE>
+__device__ inline float march_forward(const uint32_t* sv, const SegPos& g, float kfirst, float klast, float hx,
+                                      float hy, float hz, float r_hi, float r_lo) {
   float S = 0.0f;
-  for (float kf = g.k1; kf >= g.k0; kf -= 1.0f) {
+  for (float kf = klast; kf >= kfirst; kf -= (float)STRIDE) {
     const float x = coord<CLAMP>(kf, g.dx, g.px, hx);
     const float y = coord<CLAMP>(kf, g.dy, g.py, hy);
     const float z = coord<CLAMP>(kf, g.dz, g.pz, hz);
@@ -693,7 +696,11 @@ __device__ inline double fx_scale(unsigned vmax_bits, double coef) {
 // vol: the padded working volume, FP32 values or 16-bit pairs (FMT).
 // FX = false: partial sums to part[angle][rank][ray] (slots per angle);
 // FX = true: fixed-point adds into pfx[angle][pixel].
-template <int B, int FMT, bool FX>
+// LP = 2: two neighbouring lanes share a segment, one taking its even and
+// the other its odd samples (Horner with r^2 each; the pair's sum is
+// S_even + r S_odd).  Their samples are half a voxel apart, so they often
+// read the same LDS words, which the LDS serves as one broadcast.
+template <int B, int FMT, bool FX, int LP>
 __global__ __launch_bounds__(256) void k_forward_box(MarchParams P, BoxParams Bp, const uint32_t* __restrict__ vol,
                                                      float* __restrict__ part, int64_t slots,
                                                      unsigned long long* __restrict__ pfx,
@@ -724,15 +731,30 @@ __global__ __launch_bounds__(256) void k_forward_box(MarchParams P, BoxParams Bp
     scale = fx_scale(vm, fx_coef);
   }
   unsigned long long* row = pfx + (int64_t)a * Bp.npix;
-  for (int si = Bp.box_begin[b] + threadIdx.x; si < s_end; si += blockDim.x) {
+  const int part_of = LP == 2 ? (int)(threadIdx.x & 1u) : 0;
+  for (int si = Bp.box_begin[b] + (int)threadIdx.x / LP; si < s_end; si += (int)blockDim.x / LP) {
     const float4 pw = Bp.seg.pw[si], dn = Bp.seg.dn[si];
     const SegPos g = seg_pos(pw, dn, __float_as_int(dn.w), f, c, s, sc, ss, P.step);
-    const float S = seg_inside(g, hx, hy, hz) ? march_forward<SY, SZ, false, FMT>(sv, g, hx, hy, hz, P.r_hi, P.r_lo)
-                                              : march_forward<SY, SZ, true, FMT>(sv, g, hx, hy, hz, P.r_hi, P.r_lo);
+    float S;
+    if constexpr (LP == 1) {
+      S = seg_inside(g, hx, hy, hz)
+              ? march_forward<SY, SZ, false, FMT, 1>(sv, g, g.k0, g.k1, hx, hy, hz, P.r_hi, P.r_lo)
+              : march_forward<SY, SZ, true, FMT, 1>(sv, g, g.k0, g.k1, hx, hy, hz, P.r_hi, P.r_lo);
+    } else {
+      // this lane's samples: k0 + part_of, then every second one (none if
+      // the segment is shorter); both lanes of a pair take the same branch
+      const float kfirst = g.k0 + (float)part_of;
+      const float klast = kfirst + 2.0f * floorf((g.k1 - kfirst) * 0.5f);
+      S = seg_inside(g, hx, hy, hz)
+              ? march_forward<SY, SZ, false, FMT, 2>(sv, g, kfirst, klast, hx, hy, hz, P.r2_hi, P.r2_lo)
+              : march_forward<SY, SZ, true, FMT, 2>(sv, g, kfirst, klast, hx, hy, hz, P.r2_hi, P.r2_lo);
+      const float odd = __shfl_xor(S, 1);
+      S = fmaf(odd, P.r_hi, fmaf(odd, P.r_lo, S));
+    }
     const float v = pw.w * S;
     if constexpr (FX) {
       // the slot rank * n_rays + pupil * npix + pixel, modulo npix, is the pixel
-      if (finite && v != 0.0f)
+      if (part_of == 0 && finite && v != 0.0f)
         atomicAdd(row + (unsigned)Bp.seg.idx[si] % (unsigned)Bp.npix,
                   (unsigned long long)__double2ll_rn((double)v * scale));
     } else {
@@ -845,13 +867,18 @@ struct FwdOut {
   unsigned long long* pfx;  // fixed-point projections (fx = true)
   const unsigned* vmax;
   double fx_coef;
+  int lanes;                // lanes per segment (fx = true): 1 or 2
 };
 
 template <int B, int FMT, bool FX>
 static void launch_forward_box_f(dim3 grid, hipStream_t s, const MarchParams& P, const BoxParams& Bp,
                                  const uint32_t* vol, const FwdOut& o) {
-  hipLaunchKernelGGL((k_forward_box<B, FMT, FX>), grid, dim3(256), 0, s, P, Bp, vol, o.part, o.slots, o.pfx, o.vmax,
-                     o.fx_coef);
+  if (FX && o.lanes == 2)
+    hipLaunchKernelGGL((k_forward_box<B, FMT, true, 2>), grid, dim3(256), 0, s, P, Bp, vol, o.part, o.slots, o.pfx,
+                       o.vmax, o.fx_coef);
+  else
+    hipLaunchKernelGGL((k_forward_box<B, FMT, FX, 1>), grid, dim3(256), 0, s, P, Bp, vol, o.part, o.slots, o.pfx,
+                       o.vmax, o.fx_coef);
 }
 
 template <int B, bool FX>
@@ -923,7 +950,11 @@ static vam_status forward_box_fx(vam_geometry* h, const MarchParams& P, PT* proj
   const double coef = D.step / D.n_pupil * (double)h->pix_samples_max;
   if (h->n_boxes > 0) {
     const BoxParams Bp = box_params(h, h->seg_fwd, na, h->xcd_forward);
-    const FwdOut o{nullptr, 0, pfx, h->vol_absmax, coef};
+    // two lanes per segment halve the FP32 loop's LDS bank conflicts (it is
+    // bound by its LDS reads); the 16-bit pair loops are bound by VALU issue,
+    // which the pairing's per-segment work only adds to
+    const int lanes = h->forward_lanes ? h->forward_lanes : (fmt == kVolF32 ? 2 : 1);
+    const FwdOut o{nullptr, 0, pfx, h->vol_absmax, coef, lanes};
     launch_forward_box_edge<true>(h->boxes.B, work_grid(h->n_boxes, na, Bp.xcd), s, P, Bp, fmt, vol, o);
   }
   hipLaunchKernelGGL(k_fx_store<PT>, dim3((unsigned)std::max<int64_t>((n + 255) / 256, 1)), dim3(256), 0, s, pfx,
@@ -959,7 +990,7 @@ static vam_status forward_box_t(vam_geometry* h, const MarchParams& P0, PT* proj
     P.a0 = P0.a0 + c0;
     if (h->n_boxes > 0) {
       const BoxParams Bp = box_params(h, h->seg_fwd, nc, h->xcd_forward);
-      const FwdOut o{h->seg_part, slots, nullptr, nullptr, 0.0};
+      const FwdOut o{h->seg_part, slots, nullptr, nullptr, 0.0, 1};
       launch_forward_box_edge<false>(h->boxes.B, work_grid(h->n_boxes, nc, Bp.xcd), s, P, Bp, fmt,
                                      (const uint32_t*)h->vol_pad, o);
     }

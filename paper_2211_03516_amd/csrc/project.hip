@@ -293,6 +293,9 @@ MarchParams march_params(const vam_geometry* h, int a0) {
   const double r = std::exp(-D.alpha * D.step);
   P.r_hi = (float)r;
   P.r_lo = (float)(r - (double)P.r_hi);
+  const double r2 = std::exp(-2.0 * D.alpha * D.step);
+  P.r2_hi = (float)r2;
+  P.r2_lo = (float)(r2 - (double)P.r2_hi);
   P.sx4 = 4 * P.sx;
   P.sxy4 = 4 * P.sxy;
   P.vol_bytes = (int)std::min<int64_t>(h->pad_voxels * 4, 0x7fffffff);

@@ -369,6 +369,7 @@ vam_status vam_setup_geometry(const vam_geometry_desc* desc, hipStream_t stream,
   h->seg_order = 11;  // pixel classes (u mod 3, v mod 2), length-sorted runs (fastest measured)
   h->deposit_threads = 256;
   h->xcd_deposit = 8;  // XCD-aware deposit order, angles in blocks of 8 (fastest measured)
+  h->forward_lanes = 0;  // by volume format: 2 for FP32, 1 for 16-bit pairs (fastest measured)
   h->angles.resize(desc->n_angles);
   for (int a = 0; a < desc->n_angles; ++a)
     h->angles[a] = desc->angles_rad ? desc->angles_rad[a] : 2.0 * M_PI * a / desc->n_angles;
@@ -507,6 +508,9 @@ vam_status vam_set_variant(vam_geometry_t h, int32_t op, int32_t variant) {
   } else if (op == 8 || op == 9) {
     if (variant < 0 || variant > 4096) return fail(VAM_ERR_INVALID_ARG, "angle block must be in [0, 4096]");
     (op == 8 ? h->xcd_deposit : h->xcd_forward) = variant;
+  } else if (op == 10) {
+    if (variant < 0 || variant > 2) return fail(VAM_ERR_INVALID_ARG, "lanes per segment must be 0, 1 or 2");
+    h->forward_lanes = variant;
   } else {
     return fail(VAM_ERR_INVALID_ARG, "unknown operator %d", op);
   }

@@ -74,6 +74,7 @@ struct MarchParams {
   float step;
   float nb;            // -alpha log2(e)
   float r_hi, r_lo;    // exp(-alpha step) split into two floats (hi + lo)
+  float r2_hi, r2_lo;  // exp(-2 alpha step), the same way
   int sx4, sxy4;       // padded strides in bytes
   int vol_bytes;       // size of the padded FP32 working volume in bytes
 };
@@ -140,6 +141,7 @@ struct vam_geometry {
   int64_t samples_per_pass;
   int32_t adjoint_variant;
   int32_t forward_variant;
+  int32_t forward_lanes;          // lanes per segment in the fixed-point box forward: 1, 2, or 0 (by format)
 };
 
 namespace vam {

@@ -398,6 +398,40 @@ def test_fixed_point_forward():
     g.close()
 
 
+def test_forward_lanes_per_segment():
+    """The fixed-point forward with two lanes per segment (alternate samples,
+    each lane's Horner sum over r^2, combined as S_even + r S_odd) and with
+    one, against the oracle: signed FP32, BF16 and FP16 volumes,
+    every box edge, and a strongly absorbing resin (r far from 1), where a
+    wrong power of r on any part would show."""
+    n = 40
+    for alpha in (0.02, 0.6):
+        p = c2_small(n, n_pupil=4, n_angles=5, alpha=alpha)
+        g = gpu_geom(p)
+        og = oracle.Geometry(p)
+        rng = synth.SplitMix64(29)
+        x = rng.uniform(n ** 3).reshape(n, n, n) - 0.3
+        ref = oracle.forward(og, x)
+        for lanes in (1, 2):
+            g.set_forward_lanes(lanes)
+            for edge in (8, 16, 12):
+                g.set_box_edge(edge)
+                check(g.forward(to_dev(x)).cpu().numpy(), ref,
+                      what="%d lanes, alpha %g, edge %d" % (lanes, alpha, edge))
+            P1 = g.forward(to_dev(x))
+            assert torch.equal(P1, g.forward(to_dev(x)))
+            for dt, tdt in (("bf16", torch.bfloat16), ("f16", torch.float16)):
+                xs = torch.from_numpy(x).to(tdt)
+                check(g.forward(xs.to(DEV)).cpu().numpy(), oracle.forward(og, xs.double().numpy()),
+                      what="%d lanes, alpha %g, %s pairs" % (lanes, alpha, dt))
+        with pytest.raises(vam.VamError):
+            g.set_forward_lanes(4)
+        # the default picks by format (two lanes for FP32): the same bits
+        g.set_forward_lanes(0)
+        assert torch.equal(g.forward(to_dev(x)), P1)
+        g.close()
+
+
 def test_box_edges_agree():
     p = c2_small(48, n_pupil=4, n_angles=6)
     g = gpu_geom(p)
