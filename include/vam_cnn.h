@@ -39,9 +39,12 @@ typedef struct vam_cnn* vam_cnn_t;
 
 /* Create a network of `layers` (>= 2) convolutions with `channels` (a
  * multiple of 8, <= 64) hidden channels for H x W images and batches of at
- * most `max_batch` images; allocates the workspace (~(330 + 9 * 4 channels)
- * bytes per pixel of a batch) on the current device.  Parameters start at
- * zero; set them with vam_cnn_set_params. */
+ * most `max_batch` images; allocates the workspace on the current device:
+ * ~(2 (8 + (layers - 1) channels) + 4 channels + 32) bytes per pixel of a
+ * batch, plus 256 x 9 x channels^2 x 4 bytes of weight-gradient partials
+ * (the convolutions gather their im2col tiles on the fly, nothing of
+ * 9 x channels per pixel is stored).  Parameters start at zero; set them
+ * with vam_cnn_set_params. */
 vam_status vam_cnn_create(int32_t layers, int32_t channels, int32_t height, int32_t width, int32_t max_batch,
                           float in_scale0, float in_scale1, vam_cnn_t* out);
 vam_status vam_cnn_destroy(vam_cnn_t h);

@@ -1,10 +1,14 @@
 // Learned initialiser: a small 3x3 convolutional network trained and run on
 // MFMA matrix cores (gfx950 v_mfma_f32_32x32x16_bf16).
 //
-// Every convolution is an explicit im2col followed by one GEMM:
+// Every convolution is one GEMM over the im2col matrix of its input:
 //   forward          z[p][co]     = sum_kc col(a)[p][kc]   W[co][kc]
 //   data gradient    da[p][ci]    = sum_kc col(g)[p][kc]   Wflip[ci][kc]
 //   weight gradient  dW^T[kc][co] = sum_p  col(a)[p][kc]   g[p][co]
+// Every GEMM gathers its col tiles straight from the NHWC activations (or
+// gradients) while staging them in LDS: no im2col matrix is written to
+// memory.  The weight gradient stages both operands transposed (pixels
+// along k).
 // with p a pixel of the batch, kc = (tap, channel) and Wflip the kernel
 // turned by 180 degrees with input and output channels swapped (the
 // transposed convolution as a convolution).  Activations are NHWC BF16 with
@@ -53,17 +57,68 @@ struct GemmArgs {
   const float* bias;         // EPI_RELU_BF16, EPI_BIAS_F32
   const uint16_t* mask;      // EPI_MASK_BF16: [M][ldm]
   int ldm;
+  const uint16_t* X;         // CONV: A = col(X), X NHWC [M pixels][cp]; CONVT: A = col(X)^T
+  int H, W, cp;              // CONV, CONVT: image size, padded channels of X
+  const uint16_t* G;         // CONVT: B = G^T, G NHWC [pixels][cpg]
+  int cpg;
+  int ones_row;              // CONVT: A row of ones (the bias gradient's column sums)
 };
+
+// CONVT staging of a tile of 8 R rows x 32 pixels (k0 ..): work item (rc,
+// pp) loads the 8-channel chunk `c` of pixels k0 + pp and k0 + pp + 1 of
+// `src` (channels per pixel `cp`) shifted by (dy, dx), zero where `ok` is
+// false or the shifted pixel leaves the image, and writes element j of both
+// as one 32-bit word at tile[(8 rc + j) LDK + pp].
+__device__ inline void stage_t(uint16_t* tile, int rc, int pp, const uint16_t* src, int64_t k0, int cp, int c,
+                               int dy, int dx, bool ok, int H, int W) {
+  uint32_t w[2][4];
+#pragma unroll
+  for (int e = 0; e < 2; ++e) {
+    uint4 v = make_uint4(0, 0, 0, 0);
+    const int64_t p = k0 + pp + e;
+    if (ok) {
+      const int x = (int)(p % W), y = (int)((p / W) % H);
+      if (y + dy >= 0 && y + dy < H && x + dx >= 0 && x + dx < W)
+        v = *(const uint4*)(src + (p + dy * W + dx) * cp + c);
+    }
+    w[e][0] = v.x;
+    w[e][1] = v.y;
+    w[e][2] = v.z;
+    w[e][3] = v.w;
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    *(uint32_t*)(tile + (8 * rc + 2 * q) * LDK + pp) = (w[0][q] & 0xffffu) | (w[1][q] << 16);
+    *(uint32_t*)(tile + (8 * rc + 2 * q + 1) * LDK + pp) = (w[0][q] >> 16) | (w[1][q] & 0xffff0000u);
+  }
+}
 
 // C = epilogue(sum_k A(m, k) B(k, n)), 128 x 64 output tile per workgroup,
 // four waves of 32 rows x 64 columns (two 32 x 32 MFMA blocks each).
-template <bool TA, bool TB, int EPI>
+// CONV: A(m, k) = X[pixel m shifted by tap][c], k = tap cp + c (tap = 3
+// (dy + 1) + dx + 1), zero outside the image and for k >= 9 cp: the im2col
+// matrix, gathered 8 channels (16 bytes) at a time while it is staged.
+// CONVT: A(m, k) = the same with m = tap cp + c and k the pixel, and
+// B(k, n) = G[pixel k][n] (the weight gradient's operands); row ones_row of
+// A is all ones, so that row of C is the column sums of G (the bias
+// gradient).
+template <bool TA, bool TB, int EPI, bool CONV, bool CONVT = false>
 __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
   __shared__ __attribute__((aligned(16))) uint16_t As[BM * LDK];
   __shared__ __attribute__((aligned(16))) uint16_t Bs[BN * LDK];
   const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
   const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
   const int64_t kbase = (int64_t)blockIdx.z * g.K;
+  // CONV: the image row and column of this thread's two A rows
+  int cy[2] = {0, 0}, cx[2] = {0, 0};
+  if (CONV) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int p = m0 + (t >> 2) + 64 * i;
+      cx[i] = p % g.W;
+      cy[i] = (p / g.W) % g.H;
+    }
+  }
   f32x16 acc0, acc1;
   for (int r = 0; r < 16; ++r) {
     acc0[r] = 0.0f;
@@ -71,7 +126,37 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
   }
   for (int kt = 0; kt < g.K; kt += BK) {
     const int64_t k0 = kbase + kt;
-    if (!TA) {
+    if (CONVT) {
+      {
+        const int rc = t >> 4, pp = (t & 15) * 2, kc = m0 + 8 * rc;
+        if (kc == g.ones_row) {
+          // rows ones_row .. + 7: ones, then zeros (bf16 1.0 = 0x3f80)
+          *(uint32_t*)(As + (8 * rc) * LDK + pp) = 0x3f803f80u;
+#pragma unroll
+          for (int j = 1; j < 8; ++j) *(uint32_t*)(As + (8 * rc + j) * LDK + pp) = 0u;
+        } else {
+          const int tap = kc / g.cp, c = kc - tap * g.cp;
+          stage_t(As, rc, pp, g.X, k0, g.cp, c, tap / 3 - 1, tap % 3 - 1, kc < g.M && tap < 9, g.H, g.W);
+        }
+      }
+      if (t < 128) {
+        const int rc = t >> 4, pp = (t & 15) * 2, co = n0 + 8 * rc;
+        stage_t(Bs, rc, pp, g.G, k0, g.cpg, co, 0, 0, co < g.cpg, g.H, g.W);
+      }
+    } else if (CONV) {
+      const int kc = (int)k0 + (t & 3) * 8;
+      const int tap = kc / g.cp, c = kc - tap * g.cp;
+      const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const int row = (t >> 2) + 64 * i, p = m0 + row;
+        const int yy = cy[i] + dy, xx = cx[i] + dx;
+        uint4 v = make_uint4(0, 0, 0, 0);
+        if (p < g.M && tap < 9 && yy >= 0 && yy < g.H && xx >= 0 && xx < g.W)
+          v = *(const uint4*)(g.X + ((int64_t)p + dy * g.W + dx) * g.cp + c);
+        *(uint4*)(As + row * LDK + (t & 3) * 8) = v;
+      }
+    } else if (!TA) {
 #pragma unroll
       for (int i = 0; i < 2; ++i) {
         const int row = (t >> 2) + 64 * i, kc = (t & 3) * 8;
@@ -85,7 +170,8 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
 #pragma unroll
       for (int q = 0; q < 16; ++q) As[(mc + q) * LDK + kr] = (m0 + mc + q < g.M) ? src[q] : (uint16_t)0;
     }
-    if (!TB) {
+    if (CONVT) {
+    } else if (!TB) {
       const int row = t >> 2, kc = (t & 3) * 8;
       uint4 v = make_uint4(0, 0, 0, 0);
       if (n0 + row < g.N) v = *(const uint4*)(g.B + (int64_t)(n0 + row) * g.ldb + k0 + kc);
@@ -128,86 +214,6 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
         ((float*)g.C)[(int64_t)blockIdx.z * g.split_stride + o] = v;
       }
     }
-  }
-}
-
-// col[p][kc] = x[pixel p shifted by tap][c], kc = tap * cp + c, zero outside
-// the image and for kc >= 9 cp; one thread per 8 channels.
-__global__ void k_im2col(const uint16_t* __restrict__ x, int64_t npix, int H, int W, int cp, int kp,
-                         uint16_t* __restrict__ col) {
-  const int chunks = kp >> 3;
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= npix * chunks) return;
-  const int64_t p = i / chunks;
-  const int k = (int)(i - p * chunks) * 8;
-  uint4 v = make_uint4(0, 0, 0, 0);
-  if (k < 9 * cp) {
-    const int tap = k / cp, c = k - tap * cp;
-    const int w = (int)(p % W), h = (int)((p / W) % H);
-    const int hh = h + tap / 3 - 1, ww = w + tap % 3 - 1;
-    if (hh >= 0 && hh < H && ww >= 0 && ww < W) {
-      const int64_t q = p + (int64_t)(hh - h) * W + (ww - w);
-      v = *(const uint4*)(x + q * cp + c);
-    }
-  }
-  *(uint4*)(col + p * kp + k) = v;
-}
-
-// The same matrix transposed, colT[kc][p], for the weight gradient (whose
-// GEMM then reads both operands along the pixel sum).  A workgroup moves a
-// tile of 64 pixels x 64 columns through LDS: 16-byte reads of 8 channels
-// of a pixel, 16-byte writes of 8 pixels of a column.
-__global__ __launch_bounds__(256) void k_im2col_t(const uint16_t* __restrict__ x, int64_t npix, int H, int W,
-                                                  int cp, int kp, uint16_t* __restrict__ colT) {
-  constexpr int TP = 64, TK = 64, LDP = TP + 8;
-  __shared__ __attribute__((aligned(16))) uint16_t tile[TK * LDP];
-  const int64_t p0 = (int64_t)blockIdx.x * TP;
-  const int k0 = blockIdx.y * TK;
-  const int t = threadIdx.x;
-#pragma unroll
-  for (int h2 = 0; h2 < 2; ++h2) {
-    const int pl = (t >> 3) + 32 * h2, cl = (t & 7) * 8;
-    const int64_t p = p0 + pl;
-    const int k = k0 + cl;
-    uint4 v = make_uint4(0, 0, 0, 0);
-    if (p < npix && k < kp && k < 9 * cp) {
-      const int tap = k / cp, c = k - tap * cp;
-      const int w = (int)(p % W), h = (int)((p / W) % H);
-      const int hh = h + tap / 3 - 1, ww = w + tap % 3 - 1;
-      if (hh >= 0 && hh < H && ww >= 0 && ww < W) {
-        const int64_t q = p + (int64_t)(hh - h) * W + (ww - w);
-        v = *(const uint4*)(x + q * cp + c);
-      }
-    }
-    const uint32_t w4[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      tile[(cl + 2 * q) * LDP + pl] = (uint16_t)(w4[q] & 0xffffu);
-      tile[(cl + 2 * q + 1) * LDP + pl] = (uint16_t)(w4[q] >> 16);
-    }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int h2 = 0; h2 < 2; ++h2) {
-    const int row = (t >> 3) + 32 * h2, pc = (t & 7) * 8;
-    const int k = k0 + row;
-    const int64_t p = p0 + pc;
-    if (k < kp && p < npix)  // npix is a multiple of 32, so 8 pixels are in range together
-      *(uint4*)(colT + (int64_t)k * npix + p) = *(const uint4*)(tile + row * LDP + pc);
-  }
-}
-
-// gT[c][p] = g[p][c] (c < cp, a multiple of 8).
-__global__ void k_transpose_g(const uint16_t* __restrict__ g, int64_t npix, int cp, uint16_t* __restrict__ gT) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= npix * (cp >> 3)) return;
-  const int64_t j = i / npix, p = i - j * npix;
-  const uint4 v = *(const uint4*)(g + p * cp + j * 8);
-  const uint32_t w4[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    gT[(j * 8 + 2 * q) * npix + p] = (uint16_t)(w4[q] & 0xffffu);
-    gT[(j * 8 + 2 * q + 1) * npix + p] = (uint16_t)(w4[q] >> 16);
   }
 }
 
@@ -259,65 +265,47 @@ __global__ __launch_bounds__(256) void k_loss(const float* __restrict__ z, int l
   if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
 }
 
-__global__ void k_sum_in_order(const double* part, int n, double scale, double* out) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// *out = scale * sum of part[0 .. n): thread j adds part[j], part[j + 256],
+// ... in order, then a fixed-shape tree adds the 256 sums (one workgroup of
+// 256 threads; the same order on every call).
+__global__ __launch_bounds__(256) void k_sum_in_order(const double* part, int n, double scale, double* out) {
+  __shared__ double sh[256];
   double s = 0.0;
-  for (int i = 0; i < n; ++i) s += part[i];
-  *out = s * scale;
-}
-
-// Per-block column sums of g[p][c] (c < cp, cp a multiple of 8 and at most
-// 64) over rows [b R, (b + 1) R): each thread reads 8 channels of a row at
-// a time (16 B), then the block adds its threads' sums per channel in a
-// fixed order.
-__global__ __launch_bounds__(256) void k_colsum(const uint16_t* __restrict__ g, int64_t npix, int cp, int64_t rows,
-                                                float* __restrict__ part) {
-  __shared__ float sh[256 * 8];
-  const int chunks = cp >> 3;
-  const int per = 256 / chunks;  // rows in flight
-  const int c8 = threadIdx.x % chunks, j = threadIdx.x / chunks;
-  const int64_t r0 = (int64_t)blockIdx.x * rows, r1 = min(r0 + rows, npix);
-  float acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  if (j < per)
-    for (int64_t p = r0 + j; p < r1; p += per) {
-      const uint4 v = *(const uint4*)(g + p * cp + c8 * 8);
-      const uint32_t w[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        acc[2 * q] += __uint_as_float(w[q] << 16);
-        acc[2 * q + 1] += __uint_as_float(w[q] & 0xffff0000u);
-      }
-    }
-#pragma unroll
-  for (int q = 0; q < 8; ++q) sh[threadIdx.x * 8 + q] = acc[q];
+  for (int i = threadIdx.x; i < n; i += 256) s += part[i];
+  sh[threadIdx.x] = s;
   __syncthreads();
-  if ((int)threadIdx.x < cp) {
-    const int c = threadIdx.x, cc = c >> 3, q = c & 7;
-    float t = 0.0f;
-    for (int jj = 0; jj < per; ++jj) t += sh[(jj * chunks + cc) * 8 + q];
-    part[(int64_t)blockIdx.x * cp + c] = t;
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
   }
+  if (threadIdx.x == 0) *out = sh[0] * scale;
 }
 
-// grad[boff + c] = sum over blocks (in order) of part[b][c], c < cout
-__global__ void k_bias_reduce(const float* part, int nblk, int cp, int cout, float* grad) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= cout) return;
+// grad W[co][tap][ci] = sum over splits of part[z][tap * cinp + ci][co]
+// and grad b[co] = sum over splits of part[z][kp][co] (the row of ones)
+// (part entry o = kc * ldc + co).  A workgroup takes 64 consecutive entries
+// o; its four waves add the splits z = w, w + 4, ... (w = wave) in order,
+// reading 64 consecutive floats per split, and the four sums are added in
+// wave order: a fixed order on every call.
+__global__ __launch_bounds__(256) void k_wgrad_reduce(const float* part, int splits, int64_t stride, int ldc, int cinp,
+                                                      int cin, int cout, int kp, float* grad, float* bgrad) {
+  __shared__ double sh[4][64];
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int64_t o = (int64_t)blockIdx.x * 64 + l;
   double s = 0.0;
-  for (int b = 0; b < nblk; ++b) s += part[(int64_t)b * cp + c];
-  grad[c] = (float)s;
-}
-
-// grad W[co][tap][ci] = sum over splits (in order) of part[z][tap * cinp + ci][co]
-__global__ void k_wgrad_reduce(const float* part, int splits, int64_t stride, int ldc, int cinp, int cin, int cout,
-                               float* grad) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= cout * 9 * cin) return;
-  const int ci = i % cin, tap = (i / cin) % 9, co = i / (9 * cin);
-  const int64_t o = (int64_t)(tap * cinp + ci) * ldc + co;
-  double s = 0.0;
-  for (int z = 0; z < splits; ++z) s += part[z * stride + o];
-  grad[i] = (float)s;
+  if (o < stride)
+    for (int z = w; z < splits; z += 4) s += part[z * stride + o];
+  sh[w][l] = s;
+  __syncthreads();
+  if (w != 0 || o >= stride) return;
+  const int kc = (int)(o / ldc), co = (int)(o - (int64_t)kc * ldc);
+  const int tap = kc / cinp, ci = kc - tap * cinp;
+  const float v = (float)(((sh[0][l] + sh[1][l]) + sh[2][l]) + sh[3][l]);
+  if (co >= cout) return;  // padding
+  if (kc == kp)
+    bgrad[co] = v;
+  else if (tap < 9 && ci < cin)
+    grad[(co * 9 + tap) * cin + ci] = v;
 }
 
 // Forward weights wb[co][kc] (kc = tap * cinp + ci) and, for the data
@@ -365,13 +353,10 @@ struct vam_cnn {
   std::vector<uint16_t*> wb, wf;   // per layer (index l - 1)
   std::vector<uint16_t*> act;      // a_0 .. a_{L-1}
   float* z;
-  uint16_t* col;
   uint16_t* g[2];
   float* part;
-  float* bpart;
   double* lpart;
   double* loss;
-  int64_t col_elems;
   int adam_t;
 };
 
@@ -384,8 +369,8 @@ static inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
 static bool valid(const vam_cnn* h) { return h && h->magic == kCnnMagic; }
 
 static void free_cnn(vam_cnn* h) {
-  std::vector<void*> ptrs = {h->master, h->m1, h->m2, h->grad, h->z, h->col, h->g[0], h->g[1],
-                             h->part, h->bpart, h->lpart, h->loss};
+  std::vector<void*> ptrs = {h->master, h->m1, h->m2, h->grad, h->z, h->g[0], h->g[1],
+                             h->part, h->lpart, h->loss};
   for (auto p : h->wb) ptrs.push_back(p);
   for (auto p : h->wf) ptrs.push_back(p);
   for (auto p : h->act) ptrs.push_back(p);
@@ -395,18 +380,11 @@ static void free_cnn(vam_cnn* h) {
   delete h;
 }
 
-template <bool TA, bool TB, int EPI>
+template <bool TA, bool TB, int EPI, bool CONV = false, bool CONVT = false>
 static vam_status gemm(const GemmArgs& a, int splits, hipStream_t s) {
   const dim3 grid((unsigned)((a.M + BM - 1) / BM), (unsigned)((a.N + BN - 1) / BN), (unsigned)splits);
-  hipLaunchKernelGGL((k_gemm<TA, TB, EPI>), grid, dim3(256), 0, s, a);
+  hipLaunchKernelGGL((k_gemm<TA, TB, EPI, CONV, CONVT>), grid, dim3(256), 0, s, a);
   VAM_HIP_TRY(hipGetLastError(), "launching a CNN GEMM");
-  return VAM_OK;
-}
-
-static vam_status im2col(const uint16_t* x, int64_t npix, int H, int W, int cp, int kp, uint16_t* col,
-                         hipStream_t s) {
-  hipLaunchKernelGGL(k_im2col, dim3(nblocks(npix * (kp / 8), 256)), dim3(256), 0, s, x, npix, H, W, cp, kp, col);
-  VAM_HIP_TRY(hipGetLastError(), "launching im2col");
   return VAM_OK;
 }
 
@@ -435,10 +413,11 @@ static vam_status forward(vam_cnn* h, const float* x, int n, hipStream_t s) {
   VAM_HIP_TRY(hipGetLastError(), "launching the input packing");
   for (int l = 1; l <= h->L; ++l) {
     const int i = l - 1;
-    CNN_TRY(im2col(h->act[i], npix, h->H, h->W, h->cinp[i], h->kp[i], h->col, s));
     GemmArgs a = {};
-    a.A = h->col;
-    a.lda = h->kp[i];
+    a.X = h->act[i];
+    a.H = h->H;
+    a.W = h->W;
+    a.cp = h->cinp[i];
     a.B = h->wb[i];
     a.ldb = h->kp[i];
     a.M = (int)npix;
@@ -448,11 +427,11 @@ static vam_status forward(vam_cnn* h, const float* x, int n, hipStream_t s) {
     if (l < h->L) {
       a.C = h->act[l];
       a.ldc = h->coutp[i];
-      CNN_TRY((gemm<false, false, EPI_RELU_BF16>(a, 1, s)));
+      CNN_TRY((gemm<false, false, EPI_RELU_BF16, true>(a, 1, s)));
     } else {
       a.C = h->z;
       a.ldc = h->coutp[i];
-      CNN_TRY((gemm<false, false, EPI_BIAS_F32>(a, 1, s)));
+      CNN_TRY((gemm<false, false, EPI_BIAS_F32, true>(a, 1, s)));
     }
   }
   return VAM_OK;
@@ -517,7 +496,6 @@ vam_status vam_cnn_create(int32_t layers, int32_t channels, int32_t height, int3
     cmax = std::max(cmax, round_up(co, 8));
   }
   h->nparam = off;
-  h->col_elems = npix * kmax;
   const unsigned lblocks = nblocks(npix, 256);
   hipError_t e = hipSuccess;
   auto alloc = [&](void** p, size_t bytes) {
@@ -536,11 +514,9 @@ vam_status vam_cnn_create(int32_t layers, int32_t channels, int32_t height, int3
     alloc((void**)&h->act[i], (size_t)npix * h->cinp[i] * 2);
   }
   alloc((void**)&h->z, (size_t)npix * h->coutp[layers - 1] * 4);
-  alloc((void**)&h->col, (size_t)h->col_elems * 2);
   alloc((void**)&h->g[0], (size_t)npix * cmax * 2);
   alloc((void**)&h->g[1], (size_t)npix * cmax * 2);
-  alloc((void**)&h->part, (size_t)kMaxSplits * kmax * cmax * 4);  // choose_splits() <= kMaxSplits
-  alloc((void**)&h->bpart, (size_t)lblocks * cmax * 4);
+  alloc((void**)&h->part, (size_t)kMaxSplits * (kmax + 1) * cmax * 4);  // choose_splits() <= kMaxSplits
   alloc((void**)&h->lpart, (size_t)lblocks * 8);
   alloc((void**)&h->loss, 8);
   if (e == hipSuccess) e = hipMemset(h->master, 0, h->nparam * 4);
@@ -667,47 +643,42 @@ vam_status vam_cnn_loss_grad(vam_cnn_t h, const float* x, const float* t, int32_
   uint16_t* gnext = h->g[1];
   hipLaunchKernelGGL(k_loss, dim3(lblocks), dim3(256), 0, s, h->z, h->coutp[L - 1], x, t, npix, h->H * h->W, h->s1,
                      gcur, h->lpart);
-  hipLaunchKernelGGL(k_sum_in_order, dim3(1), dim3(1), 0, s, h->lpart, (int)lblocks, 1.0 / (double)npix, h->loss);
+  hipLaunchKernelGGL(k_sum_in_order, dim3(1), dim3(256), 0, s, h->lpart, (int)lblocks, 1.0 / (double)npix, h->loss);
   VAM_HIP_TRY(hipGetLastError(), "launching the CNN loss");
   const int splits = choose_splits(npix);
   const int ksplit = (int)(npix / splits);
   for (int l = L; l >= 1; --l) {
     const int i = l - 1;
-    // weight gradient: dW^T[kc][co] = sum_p colT(a_{l-1})[kc][p] gT_l[co][p],
-    // both operands laid out along the pixel sum (gT in the free buffer)
-    hipLaunchKernelGGL(k_im2col_t, dim3((unsigned)((npix + 63) / 64), (unsigned)((h->kp[i] + 63) / 64)), dim3(256), 0,
-                       s, h->act[i], npix, h->H, h->W, h->cinp[i], h->kp[i], h->col);
-    hipLaunchKernelGGL(k_transpose_g, dim3(nblocks(npix * (h->coutp[i] / 8), 256)), dim3(256), 0, s, gcur, npix,
-                       h->coutp[i], gnext);
-    VAM_HIP_TRY(hipGetLastError(), "launching the transposed im2col");
+    // weight gradient: dW^T[kc][co] = sum_p col(a_{l-1})[p][kc] g_l[p][co],
+    // both operands staged along the pixel sum straight from a_{l-1} and g_l
     GemmArgs a = {};
-    a.A = h->col;
-    a.lda = (int)npix;
-    a.B = gnext;
-    a.ldb = (int)npix;
-    a.M = h->kp[i];
+    a.X = h->act[i];
+    a.H = h->H;
+    a.W = h->W;
+    a.cp = h->cinp[i];
+    a.G = gcur;
+    a.cpg = h->coutp[i];
+    // rows 0 .. kp - 1 of dW^T, then row kp = sum_p g_l[p][co] (the bias
+    // gradient, from a row of ones in A)
+    a.M = h->kp[i] + 1;
+    a.ones_row = h->kp[i];
     a.N = h->cout[i];
     a.K = ksplit;
     a.C = h->part;
     a.ldc = h->coutp[i];
-    a.split_stride = (int64_t)h->kp[i] * h->coutp[i];
-    CNN_TRY((gemm<false, false, EPI_PART_F32>(a, splits, s)));
-    const int nw = h->cout[i] * 9 * h->cin[i];
-    hipLaunchKernelGGL(k_wgrad_reduce, dim3(nblocks(nw, 256)), dim3(256), 0, s, h->part, splits, a.split_stride,
-                       h->coutp[i], h->cinp[i], h->cin[i], h->cout[i], h->grad + h->woff[i]);
-    // bias gradient: column sums of g_l
-    const int64_t rows = 2048;
-    const unsigned bblocks = nblocks(npix, (int)rows);
-    hipLaunchKernelGGL(k_colsum, dim3(bblocks), dim3(256), 0, s, gcur, npix, h->coutp[i], rows, h->bpart);
-    hipLaunchKernelGGL(k_bias_reduce, dim3(1), dim3(64), 0, s, h->bpart, (int)bblocks, h->coutp[i], h->cout[i],
+    a.split_stride = (int64_t)(h->kp[i] + 1) * h->coutp[i];
+    CNN_TRY((gemm<false, false, EPI_PART_F32, false, true>(a, splits, s)));
+    hipLaunchKernelGGL(k_wgrad_reduce, dim3(nblocks(a.split_stride, 64)), dim3(256), 0, s, h->part, splits, a.split_stride,
+                       h->coutp[i], h->cinp[i], h->cin[i], h->cout[i], h->kp[i], h->grad + h->woff[i],
                        h->grad + h->boff[i]);
     VAM_HIP_TRY(hipGetLastError(), "launching the gradient reductions");
     if (l == 1) break;
     // data gradient through the ReLU of a_{l-1}
-    CNN_TRY(im2col(gcur, npix, h->H, h->W, h->coutp[i], h->kpb[i], h->col, s));
     GemmArgs d = {};
-    d.A = h->col;
-    d.lda = h->kpb[i];
+    d.X = gcur;
+    d.H = h->H;
+    d.W = h->W;
+    d.cp = h->coutp[i];
     d.B = h->wf[i];
     d.ldb = h->kpb[i];
     d.M = (int)npix;
@@ -717,7 +688,7 @@ vam_status vam_cnn_loss_grad(vam_cnn_t h, const float* x, const float* t, int32_
     d.ldc = h->cinp[i];
     d.mask = h->act[i];
     d.ldm = h->cinp[i];
-    CNN_TRY((gemm<false, false, EPI_MASK_BF16>(d, 1, s)));
+    CNN_TRY((gemm<false, false, EPI_MASK_BF16, true>(d, 1, s)));
     std::swap(gcur, gnext);
   }
   if (loss_out) {

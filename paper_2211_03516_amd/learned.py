@@ -241,6 +241,37 @@ def load_checkpoint(path):
                 "meta": json.loads(bytes(z["meta"]).decode())}
 
 
+def time_network(layers, channels, n, batch, steps, log):
+    """Training steps (loss and gradients, then Adam) and forward passes per
+    second of the network on seeded random batches of n x n images (no data
+    loading): the network's own throughput."""
+    import synth
+    net = Cnn(layers, channels, n, n, max_batch=batch, in_scale=(0.05, 2.0))
+    net.set_params(synth.cnninit.he_init(layers, channels, seed=0))
+    gen = torch.Generator().manual_seed(0)
+    x = torch.rand(batch, 2, n, n, generator=gen).to(DEV)
+    t = torch.rand(batch, n, n, generator=gen).to(DEV)
+    for _ in range(5):
+        net.loss_grad(x, t, want_loss=False)
+        net.adam_step(1e-4)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        net.loss_grad(x, t, want_loss=False)
+        net.adam_step(1e-4)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    t1 = time.perf_counter()
+    for _ in range(steps):
+        net.forward(x)
+    torch.cuda.synchronize()
+    di = time.perf_counter() - t1
+    log({"phase": "timing", "image": n, "batch": batch, "steps": steps,
+         "train_images_per_s": steps * batch / dt, "train_ms_per_batch": 1e3 * dt / steps,
+         "infer_ms_per_batch": 1e3 * di / steps})
+    net.close()
+
+
 def main(argv=None):
     import argparse
     import synth
@@ -262,12 +293,17 @@ def main(argv=None):
     ap.add_argument("--eval", action="store_true", help="only evaluate the network of --resume")
     ap.add_argument("--resume", default="", help="checkpoint to start from")
     ap.add_argument("--save", default="", help="checkpoint to write after training")
+    ap.add_argument("--time-steps", type=int, default=0,
+                    help="only time this many training steps and forward passes of the network")
     a = ap.parse_args(argv)
 
     def log(d):
         print(json.dumps(d), flush=True)
 
     p = synth.workload(a.workload)
+    if a.time_steps:
+        time_network(a.layers, a.channels, a.scale or p["nx"], a.batch, a.time_steps, log)
+        return 0
     if a.scale or a.angles:
         n = a.scale or p["nx"]
         ratio = n / p["nx"]
