@@ -270,9 +270,12 @@ vam_status vam_export_rays(vam_geometry_t h, double* out);
  *                   then pixel column, then row, 10 = by class (u mod 3,
  *                   v mod 2), then ray, 11, 12, 13 = order 10, then each
  *                   run of 1024 (11, default), 512 (12) or 2048 (13)
- *                   segments by decreasing length; rebuilds the boxes.
+ *                   segments by decreasing length, 14, 15, 16 = by ray,
+ *                   then each run of 256 (14) or 1024 (15) segments, or the
+ *                   whole box (16), by decreasing length in steps of two
+ *                   samples; rebuilds the boxes.
  *   op 5, threads:  workgroup size of the box deposit, 256 (default) or 512.
- *   op 7, order:    as op 4, for the forward projection (default 0).
+ *   op 7, order:    as op 4, for the forward projection (default 16).
  *   op 8, 9:        work order of the deposit (8) or forward (9) box
  *                   kernels: 0 = boxes fastest (forward default), 1 =
  *                   XCD-aware with all angles of a box on one XCD, A >= 2 =

@@ -257,9 +257,10 @@ class Geometry:
         1 (length), 2 (pixel parity class), 3, 4 (pixel class mod 3, 4),
         5 (hashed ray index), 6 (pixel, then pupil sample), 7, 8 (order 3
         with runs of 1024 / 2048 segments by length), 9 (pupil sample,
-        column, row), 10 (pixel class u mod 3, v mod 2) or 11, 12, 13
-        (order 10 with runs of 1024 / 512 / 2048 segments by length) for the
-        deposit (or forward)."""
+        column, row), 10 (pixel class u mod 3, v mod 2), 11, 12, 13
+        (order 10 with runs of 1024 / 512 / 2048 segments by length) or 14,
+        15, 16 (ray order with runs of 256 / 1024 segments / the whole box
+        by length) for the deposit (or forward)."""
         _check(lib().vam_set_variant(self.handle, OP_SEG_ORDER_FWD if forward else OP_SEG_ORDER, int(order)))
 
     def set_forward_lanes(self, lanes):

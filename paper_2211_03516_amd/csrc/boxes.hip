@@ -264,7 +264,10 @@ static vam_status alloc_table(SegTable& t, int64_t n) {
 //  10: by class (u mod 3, v mod 2), then ray (lanes three pixels apart
 //     along a row, rows two apart);
 //  11, 12, 13: order 10, then each run of 1024 (11), 512 (12) or 2048
-//     (13) consecutive segments by decreasing length.
+//     (13) consecutive segments by decreasing length;
+//  14, 15, 16: by ray, then each run of 256 (14) or 1024 (15) segments, or
+//     the whole box (16), by decreasing length in steps of two samples
+//     (ties keep the ray order).
 static void sort_segments(std::vector<int4>& hs, const std::vector<int>& begin, int order, int nu, int nv,
                           int np) {
   auto key = [&](const int4& s, int ord) -> int64_t {
@@ -283,8 +286,9 @@ static void sort_segments(std::vector<int4>& hs, const std::vector<int>& begin, 
     }
     return r;
   };
-  const int korder = (order == 7 || order == 8) ? 3 : (order >= 11 && order <= 13) ? 10 : order;
-  const int run = (order == 7 || order == 11) ? 1024 : (order == 8 || order == 13) ? 2048 : order == 12 ? 512 : 0;
+  const int korder = (order == 7 || order == 8) ? 3 : (order >= 11 && order <= 13) ? 10 : order >= 14 ? 0 : order;
+  const int run = (order == 7 || order == 11 || order == 15) ? 1024 : (order == 8 || order == 13) ? 2048
+                : order == 12 ? 512 : order == 14 ? 256 : order == 16 ? 0x7fffffff : 0;
   for (size_t i = 0; i + 1 < begin.size(); ++i) {
     std::sort(hs.begin() + begin[i], hs.begin() + begin[i + 1],
               [&](const int4& x, const int4& y) { return key(x, korder) < key(y, korder); });

@@ -367,6 +367,7 @@ vam_status vam_setup_geometry(const vam_geometry_desc* desc, hipStream_t stream,
   h->desc = *desc;
   h->adjoint_variant = 0;
   h->seg_order = 11;  // pixel classes (u mod 3, v mod 2), length-sorted runs (fastest measured)
+  h->seg_order_fwd = 16;  // ray order, then the box by length in steps of two samples (fastest measured)
   h->deposit_threads = 256;
   h->xcd_deposit = 8;  // XCD-aware deposit order, angles in blocks of 8 (fastest measured)
   h->forward_lanes = 0;  // by volume format: 2 for FP32, 1 for 16-bit pairs (fastest measured)
@@ -496,8 +497,8 @@ vam_status vam_set_variant(vam_geometry_t h, int32_t op, int32_t variant) {
   } else if (op == 2 || op == 4 || op == 7) {
     if (op == 2 && !supported_box_edge(variant))
       return fail(VAM_ERR_INVALID_ARG, "box edge %d is not one of 8, 12, 16", variant);
-    if (op != 2 && (variant < 0 || variant > 13))
-      return fail(VAM_ERR_INVALID_ARG, "segment order must be in [0, 13]");
+    if (op != 2 && (variant < 0 || variant > 16))
+      return fail(VAM_ERR_INVALID_ARG, "segment order must be in [0, 16]");
     VAM_HIP_TRY(hipSetDevice(h->device), "hipSetDevice");
     VAM_HIP_TRY(hipDeviceSynchronize(), "synchronising before rebuilding boxes");
     (op == 2 ? h->box_edge : op == 4 ? h->seg_order : h->seg_order_fwd) = variant;

@@ -110,3 +110,30 @@ def test_failed_setup_and_first_step_allocations():
         assert float((gp - ref).abs().max()) <= 1e-5 * float(ref.abs().max())
         g2.close()
     g.close()
+
+
+def test_failed_first_forward_allocations():
+    """The forward's first call allocates its 64-bit fixed-point projections
+    and the volume maximum: either allocation failing is an error that writes
+    nothing to the output, and the next call gives the same projections as
+    a handle whose first call succeeded."""
+    p = _p(24, n_angles=4)
+    t = torch.zeros((24, 24, 24), device=DEV)
+    t[6:18, 8:16, 5:19] = 1.0
+    g0 = vam.Geometry(p)
+    ref = g0.forward(t)
+    g0.close()
+    for k in (1, 2):
+        g = vam.Geometry(p)
+        out = torch.full_like(ref, 7.0)
+        vam.debug_fail_allocations(k)
+        try:
+            with pytest.raises(vam.VamError) as e:
+                g.forward(t, out=out)
+            assert e.value.status == vam.VAM_ERR_OUT_OF_MEMORY
+        finally:
+            vam.debug_fail_allocations(0)
+        torch.cuda.synchronize()
+        assert bool((out == 7.0).all())
+        assert torch.equal(g.forward(t), ref)
+        g.close()

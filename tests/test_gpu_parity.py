@@ -584,19 +584,19 @@ def test_work_orders_agree():
 
 
 def test_segment_orders_agree():
-    # the order of the segments inside a box only decides which lane marches
-    # which segment: the forward sums each segment and then the segments of
-    # a ray in rank order (same bits for every order), and the integer
-    # deposit adds each segment's runs exactly inside a workgroup; only the
-    # FP64 atomic adds of the workgroups into the dose have a free order,
-    # which can move a result by one FP32 rounding
+    # the order of the segments inside a box only decides which lanes march
+    # which segment: the forward adds each segment's sum to its pixel as an
+    # integer (same bits for every order), and the integer deposit adds each
+    # segment's runs exactly inside a workgroup; only the FP64 atomic adds
+    # of the workgroups into the dose have a free order, which can move a
+    # result by one FP32 rounding
     p = c2_small(40, n_pupil=4, n_angles=10)
     g = gpu_geom(p)
     rng = synth.SplitMix64(16)
     x = to_dev(rng.uniform(40 ** 3).reshape(40, 40, 40))
     y = to_dev(rng.uniform(10 * 40 * 40).reshape(10, 40, 40))
     P0, D0 = g.forward(x), g.back(y)
-    for order in range(14):
+    for order in range(17):
         g.set_segment_order(order)
         g.set_segment_order(order, forward=True)
         P1, D1 = g.forward(x), g.back(y)
@@ -604,7 +604,7 @@ def test_segment_orders_agree():
         say("segment order %d: forward equal %s, deposit max rel diff %.2e" % (order, torch.equal(P0, P1), dd))
         assert torch.equal(P0, P1) and dd <= 2.0 ** -23
     with pytest.raises(vam.VamError):
-        g.set_segment_order(14)
+        g.set_segment_order(17)
     g.close()
 
 
