@@ -115,7 +115,7 @@ vam_status vam_destroy_geometry(vam_geometry_t h);
  * angle_begin+angle_count-1 from vol[nz][ny][nx].  vol_t and proj_t select
  * the element types.  Deterministic: the same inputs give the same bits.
  * Each pixel's segment sums are added in 64-bit fixed point (rounding
- * <= 2^-62 of a bound per add, see vam_set_variant, op 0) and the total is
+ * <= 2^-61 of a bound per add, see vam_set_variant, op 0) and the total is
  * rounded once; a NaN or infinity anywhere in the volume makes every
  * projection value of the call NaN.  The first call allocates
  * n_angles x n_u x n_v x 8 bytes in the handle.
@@ -240,7 +240,7 @@ vam_status vam_export_rays(vam_geometry_t h, double* out);
  *                   LDS, each segment's partial added to its pixel as a
  *                   64-bit integer (scale: a power of two from the volume's
  *                   largest |value| and the most samples of a pixel;
- *                   rounding <= 2^-62 of that bound per add; integer adds
+ *                   rounding <= 2^-61 of that bound per add; integer adds
  *                   make it deterministic); a NaN or infinity anywhere in
  *                   the volume makes every projection value NaN.  Needs
  *                   n_angles x n_u x n_v x 8 bytes, allocated on first use;

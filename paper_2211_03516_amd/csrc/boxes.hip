@@ -686,7 +686,7 @@ __device__ inline float march_forward(const uint32_t* sv, const SegPos& g, float
 // sum and every partial sum of it are at most bound = (step / n_pupil)
 // pix_samples_max V.  With the power of two scale 2^(61 - e), bound < 2^e,
 // every FP32 partial times the scale is exact in FP64 and below 2^61; it is
-// rounded to an integer (<= 1/2 off, i.e. <= bound 2^-62) and added to the
+// rounded to an integer (<= 1/2 off, i.e. <= 2^(e - 62) <= bound 2^-61) and added to the
 // pixel's 64-bit integer, which stays below 2^62: integer adds commute, so
 // the result does not depend on the order of the atomics.
 __device__ inline double fx_scale(unsigned vmax_bits, double coef) {

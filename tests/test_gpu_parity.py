@@ -390,6 +390,29 @@ def test_fixed_point_forward():
         check(g.forward(xs.to(DEV)).cpu().numpy(), oracle.forward(og, xs.double().numpy()),
               what="fixed-point forward, %s pairs" % dt)
     assert torch.count_nonzero(g.forward(torch.zeros(n, n, n, device=DEV))) == 0
+    # high dynamic range: a block of 1e8 in a U(0, 1) volume.  The integer
+    # sums against the FP32 partial sums of the same samples (variant 2):
+    # every pixel above 1e-9 of the largest, those whose rays miss the block
+    # included, agrees to FP32 level (an add's rounding is at most 2^-61 of
+    # a bound set by the largest value); against the oracle the usual
+    # element-wise bound (pixels that graze the block's faces carry the
+    # samples' FP32 position rounding times the 1e8 step)
+    hdr = rng.uniform(n ** 3).reshape(n, n, n)
+    hdr[20:24, 18:22, 21:25] = 1e8
+    Ph = g.forward(to_dev(hdr)).cpu().numpy().astype(np.float64)
+    g.set_forward_lanes(1)  # the same per-segment sums as variant 2
+    Ph1 = g.forward(to_dev(hdr)).cpu().numpy().astype(np.float64)
+    g.set_forward_lanes(0)
+    g.set_forward_variant(vam.FWD_PARTIALS)
+    Pp = g.forward(to_dev(hdr)).cpu().numpy().astype(np.float64)
+    g.set_forward_variant(vam.FWD_DEFAULT)
+    sel = np.abs(Pp) >= 1e-9 * np.abs(Pp).max()
+    for what, Px in (("one lane", Ph1), ("two lanes", Ph)):
+        rel = np.abs(Px - Pp)[sel] / np.abs(Pp)[sel]
+        say("fixed-point forward (%s), 1e8 block in U(0, 1): %d of %d pixels, max relative difference to "
+            "FP32 partial sums %.2e" % (what, sel.sum(), sel.size, rel.max()))
+        assert rel.max() <= 1e-5
+    check(Ph, oracle.forward(og, hdr), what="fixed-point forward, 1e8 block in U(0, 1)")
     bad = to_dev(x)
     bad[20, 3, 7] = float("nan")
     assert torch.isnan(g.forward(bad)).all()
