@@ -47,142 +47,77 @@ __device__ inline bool bf_positive(uint16_t h) { return h != 0 && !(h & 0x8000u)
 enum Epi { EPI_RELU_BF16 = 0, EPI_BIAS_F32 = 1, EPI_MASK_BF16 = 2, EPI_PART_F32 = 3 };
 
 struct GemmArgs {
-  const uint16_t* A;   // TA ? [Ktot][lda] : [M][lda]
-  const uint16_t* B;   // TB ? [Ktot][ldb] : [N][ldb]  (B^T rows when !TB)
+  const uint16_t* B;   // !CONVT: [N][ldb] (B^T rows: the packed weights)
   int M, N, K;         // K per split (multiple of BK)
-  int lda, ldb;
+  int ldb;
   void* C;
   int ldc;
   int64_t split_stride;      // EPI_PART_F32: elements between split partials
   const float* bias;         // EPI_RELU_BF16, EPI_BIAS_F32
   const uint16_t* mask;      // EPI_MASK_BF16: [M][ldm]
   int ldm;
-  const uint16_t* X;         // CONV: A = col(X), X NHWC [M pixels][cp]; CONVT: A = col(X)^T
-  int H, W, cp;              // CONV, CONVT: image size, padded channels of X
+  const uint16_t* X;         // !CONVT: A = col(X), X NHWC [M pixels][cp]; CONVT: A = col(X)^T
+  int H, W, cp;              // image size, padded channels of X
   const uint16_t* G;         // CONVT: B = G^T, G NHWC [pixels][cpg]
   int cpg;
   int ones_row;              // CONVT: A row of ones (the bias gradient's column sums)
 };
 
-// CONVT staging of a tile of 8 R rows x 32 pixels (k0 ..): work item (rc,
-// pp) loads the 8-channel chunk `c` of pixels k0 + pp and k0 + pp + 1 of
-// `src` (channels per pixel `cp`) shifted by (dy, dx), zero where `ok` is
-// false or the shifted pixel leaves the image, and writes element j of both
-// as one 32-bit word at tile[(8 rc + j) LDK + pp].
-__device__ inline void stage_t(uint16_t* tile, int rc, int pp, const uint16_t* src, int64_t k0, int cp, int c,
-                               int dy, int dx, bool ok, int H, int W) {
-  uint32_t w[2][4];
+// Transposed staging (CONVT) of 8 rows x 2 pixels: fetch_t loads the
+// 8-channel chunk `c` of pixels k0 + pp and k0 + pp + 1 of `src` (channels
+// per pixel `cp`) shifted by (dy, dx), zero where `ok` is false or the
+// shifted pixel leaves the image; store_t writes element j of both as one
+// 32-bit word at tile[(8 rc + j) LDK + pp].
+__device__ inline void fetch_t(uint4 (&v)[2], const uint16_t* src, int64_t k0, int pp, int cp, int c, int dy, int dx,
+                               bool ok, int H, int W) {
 #pragma unroll
   for (int e = 0; e < 2; ++e) {
-    uint4 v = make_uint4(0, 0, 0, 0);
+    v[e] = make_uint4(0, 0, 0, 0);
     const int64_t p = k0 + pp + e;
     if (ok) {
       const int x = (int)(p % W), y = (int)((p / W) % H);
       if (y + dy >= 0 && y + dy < H && x + dx >= 0 && x + dx < W)
-        v = *(const uint4*)(src + (p + dy * W + dx) * cp + c);
+        v[e] = *(const uint4*)(src + (p + dy * W + dx) * cp + c);
     }
-    w[e][0] = v.x;
-    w[e][1] = v.y;
-    w[e][2] = v.z;
-    w[e][3] = v.w;
   }
+}
+
+__device__ inline void store_t(uint16_t* tile, int rc, int pp, const uint4 (&v)[2]) {
+  const uint32_t w0[4] = {v[0].x, v[0].y, v[0].z, v[0].w}, w1[4] = {v[1].x, v[1].y, v[1].z, v[1].w};
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
-    *(uint32_t*)(tile + (8 * rc + 2 * q) * LDK + pp) = (w[0][q] & 0xffffu) | (w[1][q] << 16);
-    *(uint32_t*)(tile + (8 * rc + 2 * q + 1) * LDK + pp) = (w[0][q] >> 16) | (w[1][q] & 0xffff0000u);
+    *(uint32_t*)(tile + (8 * rc + 2 * q) * LDK + pp) = (w0[q] & 0xffffu) | (w1[q] << 16);
+    *(uint32_t*)(tile + (8 * rc + 2 * q + 1) * LDK + pp) = (w0[q] >> 16) | (w1[q] & 0xffff0000u);
   }
 }
 
 // C = epilogue(sum_k A(m, k) B(k, n)), 128 x 64 output tile per workgroup,
-// four waves of 32 rows x 64 columns (two 32 x 32 MFMA blocks each).
-// CONV: A(m, k) = X[pixel m shifted by tap][c], k = tap cp + c (tap = 3
-// (dy + 1) + dx + 1), zero outside the image and for k >= 9 cp: the im2col
-// matrix, gathered 8 channels (16 bytes) at a time while it is staged.
-// CONVT: A(m, k) = the same with m = tap cp + c and k the pixel, and
-// B(k, n) = G[pixel k][n] (the weight gradient's operands); row ones_row of
-// A is all ones, so that row of C is the column sums of G (the bias
-// gradient).
-template <bool TA, bool TB, int EPI, bool CONV, bool CONVT = false>
+// four waves of 32 rows x 64 columns (two 32 x 32 MFMA blocks each).  In
+// the !CONVT GEMMs the next k-tile's global loads are issued into registers
+// before the current tile's MFMAs and written to LDS after them (10 %
+// faster); the CONVT GEMM stages each tile just before its MFMAs (its
+// prefetching form needs more registers and ran 37 % slower).
+//  !CONVT: A(m, k) = X[pixel m shifted by tap][c], k = tap cp + c (tap =
+//   3 (dy + 1) + dx + 1), zero outside the image and for k >= 9 cp: the
+//   im2col matrix, gathered 8 channels (16 bytes) at a time; B(k, n) =
+//   B[n][k] (packed weights, ldb per row).
+//  CONVT: A(m, k) = the same with m = tap cp + c and k the pixel, and
+//   B(k, n) = G[pixel k][n] (the weight gradient's operands); row ones_row
+//   of A is all ones, so that row of C is the column sums of G (the bias
+//   gradient).
+template <int EPI, bool CONVT>
 __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
   __shared__ __attribute__((aligned(16))) uint16_t As[BM * LDK];
   __shared__ __attribute__((aligned(16))) uint16_t Bs[BN * LDK];
   const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
   const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
   const int64_t kbase = (int64_t)blockIdx.z * g.K;
-  // CONV: the image row and column of this thread's two A rows
-  int cy[2] = {0, 0}, cx[2] = {0, 0};
-  if (CONV) {
-#pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      const int p = m0 + (t >> 2) + 64 * i;
-      cx[i] = p % g.W;
-      cy[i] = (p / g.W) % g.H;
-    }
-  }
   f32x16 acc0, acc1;
   for (int r = 0; r < 16; ++r) {
     acc0[r] = 0.0f;
     acc1[r] = 0.0f;
   }
-  for (int kt = 0; kt < g.K; kt += BK) {
-    const int64_t k0 = kbase + kt;
-    if (CONVT) {
-      {
-        const int rc = t >> 4, pp = (t & 15) * 2, kc = m0 + 8 * rc;
-        if (kc == g.ones_row) {
-          // rows ones_row .. + 7: ones, then zeros (bf16 1.0 = 0x3f80)
-          *(uint32_t*)(As + (8 * rc) * LDK + pp) = 0x3f803f80u;
-#pragma unroll
-          for (int j = 1; j < 8; ++j) *(uint32_t*)(As + (8 * rc + j) * LDK + pp) = 0u;
-        } else {
-          const int tap = kc / g.cp, c = kc - tap * g.cp;
-          stage_t(As, rc, pp, g.X, k0, g.cp, c, tap / 3 - 1, tap % 3 - 1, kc < g.M && tap < 9, g.H, g.W);
-        }
-      }
-      if (t < 128) {
-        const int rc = t >> 4, pp = (t & 15) * 2, co = n0 + 8 * rc;
-        stage_t(Bs, rc, pp, g.G, k0, g.cpg, co, 0, 0, co < g.cpg, g.H, g.W);
-      }
-    } else if (CONV) {
-      const int kc = (int)k0 + (t & 3) * 8;
-      const int tap = kc / g.cp, c = kc - tap * g.cp;
-      const int dy = tap / 3 - 1, dx = tap % 3 - 1;
-#pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        const int row = (t >> 2) + 64 * i, p = m0 + row;
-        const int yy = cy[i] + dy, xx = cx[i] + dx;
-        uint4 v = make_uint4(0, 0, 0, 0);
-        if (p < g.M && tap < 9 && yy >= 0 && yy < g.H && xx >= 0 && xx < g.W)
-          v = *(const uint4*)(g.X + ((int64_t)p + dy * g.W + dx) * g.cp + c);
-        *(uint4*)(As + row * LDK + (t & 3) * 8) = v;
-      }
-    } else if (!TA) {
-#pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        const int row = (t >> 2) + 64 * i, kc = (t & 3) * 8;
-        uint4 v = make_uint4(0, 0, 0, 0);
-        if (m0 + row < g.M) v = *(const uint4*)(g.A + (int64_t)(m0 + row) * g.lda + k0 + kc);
-        *(uint4*)(As + row * LDK + kc) = v;
-      }
-    } else {
-      const int kr = t >> 3, mc = (t & 7) * 16;
-      const uint16_t* src = g.A + (k0 + kr) * (int64_t)g.lda + m0 + mc;
-#pragma unroll
-      for (int q = 0; q < 16; ++q) As[(mc + q) * LDK + kr] = (m0 + mc + q < g.M) ? src[q] : (uint16_t)0;
-    }
-    if (CONVT) {
-    } else if (!TB) {
-      const int row = t >> 2, kc = (t & 3) * 8;
-      uint4 v = make_uint4(0, 0, 0, 0);
-      if (n0 + row < g.N) v = *(const uint4*)(g.B + (int64_t)(n0 + row) * g.ldb + k0 + kc);
-      *(uint4*)(Bs + row * LDK + kc) = v;
-    } else {
-      const int kr = t >> 3, nc = (t & 7) * 8;
-      const uint16_t* src = g.B + (k0 + kr) * (int64_t)g.ldb + n0 + nc;
-#pragma unroll
-      for (int q = 0; q < 8; ++q) Bs[(nc + q) * LDK + kr] = (n0 + nc + q < g.N) ? src[q] : (uint16_t)0;
-    }
-    __syncthreads();
+  auto mma = [&]() {
 #pragma unroll
     for (int ks = 0; ks < BK; ks += 16) {
       const int kk = ks + 8 * (lane >> 5);
@@ -192,7 +127,69 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
       acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b0, acc0, 0, 0, 0);
       acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b1, acc1, 0, 0, 0);
     }
-    __syncthreads();
+  };
+  if constexpr (CONVT) {
+    // each tile staged right before its MFMAs: work item (rc, pp) moves an
+    // 8-row chunk of two pixels of A (and, t < 128, of B)
+    const int rc = t >> 4, pp = (t & 15) * 2, kc = m0 + 8 * rc, co = n0 + 8 * rc;
+    for (int kt = 0; kt < g.K; kt += BK) {
+      const int64_t k0 = kbase + kt;
+      uint4 v[2];
+      if (kc == g.ones_row) {
+        // rows ones_row .. + 7: ones, then zeros (bf16 1.0 = 0x3f80)
+        *(uint32_t*)(As + (8 * rc) * LDK + pp) = 0x3f803f80u;
+#pragma unroll
+        for (int j = 1; j < 8; ++j) *(uint32_t*)(As + (8 * rc + j) * LDK + pp) = 0u;
+      } else {
+        const int tap = kc / g.cp, c = kc - tap * g.cp;
+        fetch_t(v, g.X, k0, pp, g.cp, c, tap / 3 - 1, tap % 3 - 1, kc < g.M && tap < 9, g.H, g.W);
+        store_t(As, rc, pp, v);
+      }
+      if (t < 128) {
+        fetch_t(v, g.G, k0, pp, g.cpg, co, 0, 0, co < g.cpg, g.H, g.W);
+        store_t(Bs, rc, pp, v);
+      }
+      __syncthreads();
+      mma();
+      __syncthreads();
+    }
+  } else {
+    // the next tile's global loads are issued before the current tile's
+    // MFMAs and written to LDS after them
+    int cy[2], cx[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int p = m0 + (t >> 2) + 64 * i;
+      cx[i] = p % g.W;
+      cy[i] = (p / g.W) % g.H;
+    }
+    uint4 ra[2], rb;
+    auto fetch = [&](int64_t k0) {
+      const int kc = (int)k0 + (t & 3) * 8;
+      const int tap = kc / g.cp, c = kc - tap * g.cp;
+      const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const int p = m0 + (t >> 2) + 64 * i;
+        const int yy = cy[i] + dy, xx = cx[i] + dx;
+        ra[i] = make_uint4(0, 0, 0, 0);
+        if (p < g.M && tap < 9 && yy >= 0 && yy < g.H && xx >= 0 && xx < g.W)
+          ra[i] = *(const uint4*)(g.X + ((int64_t)p + dy * g.W + dx) * g.cp + c);
+      }
+      const int row = t >> 2;
+      rb = make_uint4(0, 0, 0, 0);
+      if (n0 + row < g.N) rb = *(const uint4*)(g.B + (int64_t)(n0 + row) * g.ldb + k0 + (t & 3) * 8);
+    };
+    fetch(kbase);
+    for (int kt = 0; kt < g.K; kt += BK) {
+#pragma unroll
+      for (int i = 0; i < 2; ++i) *(uint4*)(As + ((t >> 2) + 64 * i) * LDK + (t & 3) * 8) = ra[i];
+      *(uint4*)(Bs + (t >> 2) * LDK + (t & 3) * 8) = rb;
+      __syncthreads();
+      if (kt + BK < g.K) fetch(kbase + kt + BK);
+      mma();
+      __syncthreads();
+    }
   }
 #pragma unroll
   for (int j = 0; j < 2; ++j) {
@@ -380,10 +377,10 @@ static void free_cnn(vam_cnn* h) {
   delete h;
 }
 
-template <bool TA, bool TB, int EPI, bool CONV = false, bool CONVT = false>
+template <int EPI, bool CONVT>
 static vam_status gemm(const GemmArgs& a, int splits, hipStream_t s) {
   const dim3 grid((unsigned)((a.M + BM - 1) / BM), (unsigned)((a.N + BN - 1) / BN), (unsigned)splits);
-  hipLaunchKernelGGL((k_gemm<TA, TB, EPI, CONV, CONVT>), grid, dim3(256), 0, s, a);
+  hipLaunchKernelGGL((k_gemm<EPI, CONVT>), grid, dim3(256), 0, s, a);
   VAM_HIP_TRY(hipGetLastError(), "launching a CNN GEMM");
   return VAM_OK;
 }
@@ -427,11 +424,11 @@ static vam_status forward(vam_cnn* h, const float* x, int n, hipStream_t s) {
     if (l < h->L) {
       a.C = h->act[l];
       a.ldc = h->coutp[i];
-      CNN_TRY((gemm<false, false, EPI_RELU_BF16, true>(a, 1, s)));
+      CNN_TRY((gemm<EPI_RELU_BF16, false>(a, 1, s)));
     } else {
       a.C = h->z;
       a.ldc = h->coutp[i];
-      CNN_TRY((gemm<false, false, EPI_BIAS_F32, true>(a, 1, s)));
+      CNN_TRY((gemm<EPI_BIAS_F32, false>(a, 1, s)));
     }
   }
   return VAM_OK;
@@ -667,7 +664,7 @@ vam_status vam_cnn_loss_grad(vam_cnn_t h, const float* x, const float* t, int32_
     a.C = h->part;
     a.ldc = h->coutp[i];
     a.split_stride = (int64_t)(h->kp[i] + 1) * h->coutp[i];
-    CNN_TRY((gemm<false, false, EPI_PART_F32, false, true>(a, splits, s)));
+    CNN_TRY((gemm<EPI_PART_F32, true>(a, splits, s)));
     hipLaunchKernelGGL(k_wgrad_reduce, dim3(nblocks(a.split_stride, 64)), dim3(256), 0, s, h->part, splits, a.split_stride,
                        h->coutp[i], h->cinp[i], h->cin[i], h->cout[i], h->kp[i], h->grad + h->woff[i],
                        h->grad + h->boff[i]);
@@ -688,7 +685,7 @@ vam_status vam_cnn_loss_grad(vam_cnn_t h, const float* x, const float* t, int32_
     d.ldc = h->cinp[i];
     d.mask = h->act[i];
     d.ldm = h->cinp[i];
-    CNN_TRY((gemm<false, false, EPI_MASK_BF16, true>(d, 1, s)));
+    CNN_TRY((gemm<EPI_MASK_BF16, false>(d, 1, s)));
     std::swap(gcur, gnext);
   }
   if (loss_out) {
