@@ -134,12 +134,15 @@ vam_status vam_forward_project(vam_geometry_t h, const void* vol, vam_dtype vol_
  * are skipped (they add nothing).  The default kernel sums each (box of the
  * lab frame, angle) in 32-bit fixed point, scaled per box and angle so that
  * no partial sum can overflow (rounding <= 2^-31 of a bound on the box's
- * largest cell sum per add), then adds to an FP64 accumulator; the order of
- * those FP64 additions is unspecified (results may differ in the last bits
- * between runs).  A non-finite projection value makes the dose of the lab
- * boxes its rays cross NaN.  The angle range selects which projections
- * proj holds (one GPU's share of the angles when the work is split).
- * Errors as for vam_forward_project. */
+ * largest cell sum per add), then adds each cell to the voxel's 64-bit
+ * integer at a power-of-two scale set by the call's largest |projection
+ * value| (rounding <= 2^-61 of a bound on the voxel's dose per add); the
+ * integer adds commute, so the result is deterministic (the same bits on
+ * every run and for every segment order).  A NaN or infinity among the
+ * projection values makes the whole dose NaN.  The angle range selects
+ * which projections proj holds (one GPU's share of the angles when the
+ * work is split).  The first call allocates (nx+4)(ny+4)(nz+4) + 32 eight-
+ * byte words in the handle.  Errors as for vam_forward_project. */
 vam_status vam_back_project(vam_geometry_t h, const void* proj, vam_dtype proj_t,
                             float* dose, int32_t accumulate,
                             int32_t angle_begin, int32_t angle_count,
@@ -148,11 +151,11 @@ vam_status vam_back_project(vam_geometry_t h, const void* proj, vam_dtype proj_t
 /* vam_back_project without device allocation, for callers that cannot
  * allocate device memory (code under HIP graph capture, tight serving loops,
  * harnesses that forbid it).  Same arguments, operator and result as
- * vam_back_project; the padded FP64 accumulator of the deposit comes from a
+ * vam_back_project; the padded accumulator of the deposit comes from a
  * file-scope device array of the library (136 MiB per device, held by every
  * device the library runs on until the process ends) instead of the
  * handle.  Limit: the padded grid (nx+4)(ny+4)(nz+4) must be at most
- * 17,825,792 voxels (cubes up to 257^3), else VAM_ERR_UNSUPPORTED; the
+ * 17,825,760 voxels (cubes up to 257^3), else VAM_ERR_UNSUPPORTED; the
  * gather variant (vam_set_variant op 1 = 2) is refused the same way.  All
  * calls on one device share the array and it keeps the last call's
  * contents (each call clears it first, with a kernel): calls that overlap

@@ -207,6 +207,15 @@ static vam_status support_bound(vam_geometry* h, const BoxGrid& G, hipStream_t s
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   (void)hipFree(count);
   if (e != hipSuccess) return hip_check(e, "bounding samples per voxel support");
+  // a 4 x 4 x 3 block of cells meets at most 2 boxes along each axis (the
+  // box edge is at least 8), so all boxes together put at most 8 x the
+  // largest box_supp samples into one voxel's support
+  std::vector<int> hb(std::max(h->n_boxes, 1), 0);
+  if (h->n_boxes > 0) {
+    e = hipMemcpy(hb.data(), h->box_supp, h->n_boxes * sizeof(int), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_check(e, "reading the support bounds");
+  }
+  h->supp_bound = 8 * (int64_t)*std::max_element(hb.begin(), hb.end());
   return VAM_OK;
 }
 
@@ -689,13 +698,6 @@ __device__ inline float march_forward(const uint32_t* sv, const SegPos& g, float
 // rounded to an integer (<= 1/2 off, i.e. <= 2^(e - 62) <= bound 2^-61) and added to the
 // pixel's 64-bit integer, which stays below 2^62: integer adds commute, so
 // the result does not depend on the order of the atomics.
-__device__ inline double fx_scale(unsigned vmax_bits, double coef) {
-  const double bound = (double)__uint_as_float(vmax_bits) * coef;
-  if (!(bound > 0.0)) return 1.0;  // all partials are zero
-  int e;
-  (void)frexp(bound, &e);           // bound < 2^e
-  return ldexp(1.0, 61 - e);
-}
 
 // vol: the padded working volume, FP32 values or 16-bit pairs (FMT).
 // FX = false: partial sums to part[angle][rank][ray] (slots per angle);
@@ -1123,48 +1125,45 @@ __device__ inline void march_deposit(int* acc, const SegPos& g, float e, float h
   flush8<SY, SZ>(acc, cur, w);  // a segment has at least one sample
 }
 
+// acc: the padded dose as 64-bit integers at the scale fx_scale(*pmax,
+// dep_coef), pmax the largest |projection value| of the call (FP32 bits;
+// a NaN or infinity among them leaves acc untouched: the dose copy then
+// writes NaN everywhere).
 template <int B, typename PT, int NT>
 __global__ __launch_bounds__(NT) void k_back_box(MarchParams P, BoxParams Bp, const PT* __restrict__ proj,
-                                                 double* __restrict__ dose) {
+                                                 unsigned long long* __restrict__ acc64,
+                                                 const unsigned* __restrict__ pmax, double dep_coef) {
   // slice pitch one word longer than a slice: 3 % faster than SY * SY at
   // edge 12 (the pitch decides which LDS banks the lanes' adds share)
   constexpr int SY = Fixed<B>::WXY, SZ = SY * SY + 1, NC = SZ * Fixed<B>::WZ;
   __shared__ int acc[NC];
   __shared__ unsigned s_pvmax;
-  __shared__ int s_bad;
   int b, a;
   if (!work_item(Bp.nboxes, Bp.na, Bp.xcd, b, a)) return;
+  const unsigned pm = *pmax;
+  if (pm >= 0x7f800000u) return;  // a non-finite projection value: the dose is NaN
+  const double G = fx_scale(pm, dep_coef);
   const double2 cs = P.cs[P.a0 + a];
   const Foot f = footprint(Bp, Bp.box_id[b], cs.x, cs.y, P.cx, P.cy);
   for (int i = threadIdx.x; i < NC; i += blockDim.x) acc[i] = 0;
-  if (threadIdx.x == 0) {
-    s_pvmax = 0u;
-    s_bad = 0;
-  }
+  if (threadIdx.x == 0) s_pvmax = 0u;
   __syncthreads();
   const float hx = (float)f.WX - 1.001f, hy = (float)f.WY - 1.001f, hz = (float)f.WZ - 1.001f;
   const int64_t pbase = (int64_t)a * Bp.npix;
   const int s_end = Bp.box_begin[b + 1];
   // the box's largest |projection value| at this angle sets the scale
   float m = 0.0f;
-  bool nonfinite = false;
-  for (int si = Bp.box_begin[b] + threadIdx.x; si < s_end; si += blockDim.x) {
-    const float apv = fabsf(load_p(proj, pbase + Bp.seg.idx[si]));
-    if (apv <= 3.4028234e38f)
-      m = fmaxf(m, apv);
-    else
-      nonfinite = true;
-  }
+  for (int si = Bp.box_begin[b] + threadIdx.x; si < s_end; si += blockDim.x)
+    m = fmaxf(m, fabsf(load_p(proj, pbase + Bp.seg.idx[si])));
   atomicMax(&s_pvmax, __float_as_uint(m));  // non-negative floats order as their bits
-  if (nonfinite) atomicOr(&s_bad, 1);
   __syncthreads();
-  const bool bad = s_bad != 0;
   const int nb = Bp.box_supp[b];
   const double bound = (double)nb * Bp.w_coef * (double)__uint_as_float(s_pvmax);
   // capped below FP32's largest value (a smaller S only rounds coarser)
   const float S = bound > 0.0 ? (float)fmin((2147483648.0 - nb - 4096.0) * (1.0 - 1.0 / 4096.0) / bound, 3.0e38)
                               : 1.0f;
-  const double invS = 1.0 / (double)S;
+  // a cell's integer at the dose scale: raw / S x G, rounded (G a power of two)
+  const double toG = G / (double)S;
   const float c = (float)cs.x, s = (float)cs.y, sc = P.step * c, ss = P.step * s;
   for (int si = Bp.box_begin[b] + threadIdx.x; si < s_end; si += blockDim.x) {
     const float pv = load_p(proj, pbase + Bp.seg.idx[si]);
@@ -1180,12 +1179,30 @@ __global__ __launch_bounds__(NT) void k_back_box(MarchParams P, BoxParams Bp, co
   __syncthreads();
   for (int i = threadIdx.x; i < NC; i += blockDim.x) {
     const int raw = acc[i];
-    if (raw == 0 && !bad) continue;
+    if (raw == 0) continue;
     const int z = i / SZ, rem = i - z * SZ, y = rem / SY, x = rem - y * SY;
     if (x >= f.WX || y >= f.WY || z >= f.WZ) continue;
     const int64_t gi = ((int64_t)(f.Z0 + z) * Bp.py + (f.Y0 + y)) * Bp.px + (f.X0 + x);
-    unsafeAtomicAdd(dose + gi, bad ? __builtin_nan("") : (double)raw * invS);
+    atomicAdd(acc64 + gi, (unsigned long long)__double2ll_rn((double)raw * toG));
   }
+}
+
+// Largest |value| of the na x npix projections of a call, as FP32 bits
+// (a NaN or infinity compares above every finite value).
+template <typename PT>
+__global__ __launch_bounds__(256) void k_proj_absmax(const PT* __restrict__ proj, int64_t n, unsigned* __restrict__ pmax) {
+  unsigned m = 0u;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    m = max(m, __float_as_uint(load_p(proj, i)) & 0x7fffffffu);
+  for (int off = 32; off > 0; off >>= 1) m = max(m, (unsigned)__shfl_xor((int)m, off));
+  if ((threadIdx.x & 63) == 0) atomicMax(pmax, m);
+}
+
+// Bound on a voxel's dose per unit of the largest |projection value|: per
+// angle at most supp_bound samples meet its support, each of weight at most
+// step / n_pupil.
+double deposit_coef(const vam_geometry* h, int na) {
+  return (double)na * (double)std::max<int64_t>(h->supp_bound, 1) * h->desc.step / h->desc.n_pupil;
 }
 
 template <int B, typename PT>
@@ -1193,15 +1210,22 @@ static void launch_back_box(vam_geometry* h, const MarchParams& P, const PT* pro
                             hipStream_t s) {
   const BoxParams Bp = box_params(h, h->seg_dep, na, h->xcd_deposit);
   const dim3 grid = work_grid(h->n_boxes, na, Bp.xcd);
+  unsigned long long* a64 = (unsigned long long*)acc;
+  const unsigned* pm = (const unsigned*)(acc + h->pad_voxels);
+  const double coef = deposit_coef(h, na);
   if (h->deposit_threads == 512)
-    hipLaunchKernelGGL((k_back_box<B, PT, 512>), grid, dim3(512), 0, s, P, Bp, proj, acc);
+    hipLaunchKernelGGL((k_back_box<B, PT, 512>), grid, dim3(512), 0, s, P, Bp, proj, a64, pm, coef);
   else
-    hipLaunchKernelGGL((k_back_box<B, PT, 256>), grid, dim3(256), 0, s, P, Bp, proj, acc);
+    hipLaunchKernelGGL((k_back_box<B, PT, 256>), grid, dim3(256), 0, s, P, Bp, proj, a64, pm, coef);
 }
 
 template <typename PT>
 static void launch_back_box_t(vam_geometry* h, const MarchParams& P, const PT* proj, int na, double* acc,
                               hipStream_t s) {
+  // the largest |projection value| first (its slot was cleared with acc)
+  const int64_t n = (int64_t)na * h->desc.n_u * h->desc.n_v;
+  hipLaunchKernelGGL(k_proj_absmax<PT>, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 2048)), dim3(256), 0, s,
+                     proj, n, (unsigned*)(acc + h->pad_voxels));
   switch (h->boxes.B) {
     case 8: launch_back_box<8, PT>(h, P, proj, na, acc, s); break;
     case 12: launch_back_box<12, PT>(h, P, proj, na, acc, s); break;

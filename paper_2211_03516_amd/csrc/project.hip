@@ -264,6 +264,23 @@ __global__ void k_unpad(const AT* __restrict__ dp, float* __restrict__ dose, int
   dose[i] = accumulate ? (float)(dose[i] + d) : (float)d;
 }
 
+// The box deposit's integer dose -> caller dose: the integer over the scale,
+// plus the caller's dose if accumulating; NaN everywhere if a projection
+// value was a NaN or an infinity.
+__global__ void k_unpad_fx(const unsigned long long* __restrict__ acc, float* __restrict__ dose, int accumulate,
+                           int nx, int ny, int nz, int px, int py, const unsigned* __restrict__ pmax, double coef) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t n = (int64_t)nx * ny * nz;
+  if (i >= n) return;
+  const int x = (int)(i % nx);
+  const int y = (int)((i / nx) % ny);
+  const int z = (int)(i / ((int64_t)nx * ny));
+  const unsigned pm = *pmax;
+  const long long q = (long long)acc[((int64_t)(z + kPad) * py + (y + kPad)) * px + (x + kPad)];
+  const double d = pm < 0x7f800000u ? (double)q / fx_scale(pm, coef) : __builtin_nan("");
+  dose[i] = accumulate ? (float)(dose[i] + d) : (float)d;
+}
+
 template <typename T>
 __global__ void k_fill(T* __restrict__ p, int64_t n, T value) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -377,13 +394,15 @@ vam_status launch_back(vam_geometry* h, const void* proj, vam_dtype proj_t, floa
                                      "set the box edge again or create a new geometry");
   if (!acc) {
     if (!h->dose_pad64)
-      VAM_HIP_TRY(dev_alloc((void**)&h->dose_pad64, h->pad_voxels * sizeof(double)),
-                  "allocating the FP64 accumulator");
+      VAM_HIP_TRY(dev_alloc((void**)&h->dose_pad64, (h->pad_voxels + kAccTail) * sizeof(double)),
+                  "allocating the dose accumulator");
     acc = h->dose_pad64;
   }
-  // cleared by a kernel (no memset node when the caller captures a graph)
-  hipLaunchKernelGGL(k_fill<double>, dim3(blocks_for(h->pad_voxels, 256)), dim3(256), 0, s, acc, h->pad_voxels,
-                     0.0);
+  // cleared by a kernel (no memset node when the caller captures a graph):
+  // the dose words and the projection maximum after them (all-zero bits are
+  // 0 both as FP64 and as integers)
+  hipLaunchKernelGGL(k_fill<double>, dim3(blocks_for(h->pad_voxels + 1, 256)), dim3(256), 0, s, acc,
+                     h->pad_voxels + 1, 0.0);
   VAM_HIP_TRY(hipGetLastError(), "launching the accumulator clear");
   MarchParams P = march_params(h, a0);
   VAM_HIP_TRY(hipEventRecord(h->ev[2], s), "recording an event");
@@ -408,20 +427,26 @@ vam_status launch_back(vam_geometry* h, const void* proj, vam_dtype proj_t, floa
   VAM_HIP_TRY(hipEventRecord(h->ev[3], s), "recording an event");
   h->ev_valid[1] = 1;
   const int64_t nvox = (int64_t)D.nx * D.ny * D.nz;
-  hipLaunchKernelGGL(k_unpad<double>, dim3(blocks_for(nvox, 256)), dim3(256), 0, s, acc, dose, accumulate,
-                     D.nx, D.ny, D.nz, h->px, h->py);
+  if (variant == 0)
+    hipLaunchKernelGGL(k_unpad_fx, dim3(blocks_for(nvox, 256)), dim3(256), 0, s, (const unsigned long long*)acc, dose,
+                       accumulate, D.nx, D.ny, D.nz, h->px, h->py, (const unsigned*)(acc + h->pad_voxels),
+                       deposit_coef(h, na));
+  else
+    hipLaunchKernelGGL(k_unpad<double>, dim3(blocks_for(nvox, 256)), dim3(256), 0, s, acc, dose, accumulate,
+                       D.nx, D.ny, D.nz, h->px, h->py);
   VAM_HIP_TRY(hipGetLastError(), "launching the dose copy");
   return VAM_OK;
 }
 
 // ------------------------------------------------ allocation-free deposit --
 //
-// vam_back_project_noalloc takes the deposit's padded FP64 accumulator from
-// this file-scope device array instead of allocating it.  Each device that
+// vam_back_project_noalloc takes the deposit's padded accumulator (and the
+// kAccTail words after it) from this file-scope device array instead of
+// allocating it.  Each device that
 // loads the library holds its own copy until the process ends; its device
 // address is looked up once per device (with that device current) and kept
 // in scratch_dev, which is what host code passes to the kernels.
-constexpr int64_t kScratchDoubles = 17825792;  // 136 MiB: padded grids up to 261^3 (volumes up to 257^3)
+constexpr int64_t kScratchDoubles = 17825792;  // 136 MiB: padded grids up to 261^3 + kAccTail (volumes up to 257^3)
 constexpr int kMaxDevices = 64;
 static __device__ __align__(256) double scratch[kScratchDoubles];
 static double* scratch_dev[kMaxDevices];
@@ -483,11 +508,11 @@ vam_status vam_back_project_noalloc(vam_geometry_t h, const void* proj, vam_dtyp
   clear_error();
   vam_status st = check_common(h, proj, dose, proj_t, angle_begin, angle_count);
   if (st != VAM_OK) return st;
-  if (h->pad_voxels > kScratchDoubles)
+  if (h->pad_voxels + kAccTail > kScratchDoubles)
     return fail(VAM_ERR_UNSUPPORTED,
                 "allocation-free deposit: the padded grid (%d x %d x %d = %lld voxels) exceeds the %lld-voxel "
                 "scratch array (volumes up to 257^3)",
-                h->px, h->py, h->pz, (long long)h->pad_voxels, (long long)kScratchDoubles);
+                h->px, h->py, h->pz, (long long)h->pad_voxels, (long long)(kScratchDoubles - kAccTail));
   if (h->adjoint_variant == 2)
     return fail(VAM_ERR_UNSUPPORTED, "allocation-free deposit: the gather variant builds an inverse ray map");
   VAM_HIP_TRY(hipSetDevice(h->device), "hipSetDevice");

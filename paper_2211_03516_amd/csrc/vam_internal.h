@@ -95,7 +95,8 @@ struct vam_geometry {
   double* ray64;                 // [n_rays][kRay64Fields]
   double2* angle_cs;             // [n_angles] (cos, sin)
   float* vol_pad;                // padded FP32 working volume (forward input)
-  double* dose_pad64;            // padded FP64 dose accumulator, allocated on first use
+  double* dose_pad64;            // padded dose accumulator (+ kAccTail words), allocated on first use:
+                                 // 64-bit integers (box deposit) or FP64 (ray-driven deposit)
   // optimisation buffers, allocated on first vam_optimize_step
   float* resid;                  // [nz][ny][nx]
   float* grad;                   // [n_angles][n_v][n_u]
@@ -130,6 +131,7 @@ struct vam_geometry {
   int* box_begin;                // [n_boxes + 1] segment offsets
   int* box_id;                   // [n_boxes] linear box index (x fastest)
   int* box_supp;                 // [n_boxes] most samples of the box in any 4 x 4 x 3 block of lab unit cells
+  int64_t supp_bound;            // most samples of all boxes in any such block: <= 8 x max box_supp
   int box_cells;                 // largest rotated-box footprint in cells (LDS)
   // inverse ray map of the voxel-driven gather deposit, built on first use
   vam::BoxGrid cells;            // lab-frame unit cells
@@ -145,6 +147,24 @@ struct vam_geometry {
 };
 
 namespace vam {
+
+// The dose accumulator holds pad_voxels values and then kAccTail more words;
+// the first of them keeps the largest |projection value| of a deposit (FP32
+// bits) for its integer scale.
+constexpr int64_t kAccTail = 32;
+
+// Power-of-two scale of a 64-bit fixed-point sum whose exact value and every
+// partial sum are at most bound = |largest value| x coef in magnitude:
+// 2^(61 - e) with bound < 2^e, so that each scaled term (an FP32 or FP64
+// value times a power of two) is below 2^61 and the sum below 2^62; 1 if
+// the bound is 0.
+__device__ inline double fx_scale(unsigned max_bits, double coef) {
+  const double bound = (double)__uint_as_float(max_bits) * coef;
+  if (!(bound > 0.0)) return 1.0;
+  int e;
+  (void)frexp(bound, &e);
+  return ldexp(1.0, 61 - e);
+}
 
 vam_status fail(vam_status s, const char* fmt, ...);
 void clear_error();
@@ -172,8 +192,12 @@ vam_status launch_box_forward(vam_geometry* h, const MarchParams& P, void* proj,
                               int na, hipStream_t s);
 // the box forward's padded working volume from a BF16 or FP16 volume
 void pad_box_volume(vam_geometry* h, const void* vol, vam_dtype vol_t, hipStream_t s);
+// acc: pad_voxels + kAccTail words, cleared (pad_voxels + 1 of them) by the
+// caller; the box deposit leaves the dose there as 64-bit integers at the
+// scale fx_scale(acc[pad_voxels] bits, deposit_coef(h, na))
 vam_status launch_box_deposit(vam_geometry* h, const MarchParams& P, const void* proj, vam_dtype proj_t,
                               int na, double* acc, hipStream_t s);
+double deposit_coef(const vam_geometry* h, int na);
 void free_boxes(vam_geometry* h);
 bool supported_box_edge(int B);
 // voxel-driven gather deposit through the inverse ray map (gather.hip);
