@@ -1035,7 +1035,9 @@ vam_status launch_box_forward(vam_geometry* h, const MarchParams& P, void* proj,
 // The deposit adds 8 corner weights per sample into the (box, angle)
 // workgroup's LDS footprint in 32-bit fixed point (gfx950 adds 32-bit
 // integers in LDS ~45x faster than FP32 and ~2x faster than FP64), then adds
-// each touched cell to the padded FP64 accumulator once.  Overflow is ruled
+// each touched cell once to its voxel's 64-bit integer (a power-of-two scale
+// from the call's largest |projection value|; integer adds commute, so the
+// dose is deterministic).  Overflow in LDS is ruled
 // out per workgroup: a cell's exact sum is at most bound = n x (step /
 // n_pupil) x M, where n is the box's n_supp (the most samples of the box in
 // any 4 x 4 x 3 block of lab-frame unit cells, which holds the turned
@@ -1046,7 +1048,8 @@ vam_status launch_box_forward(vam_geometry* h, const MarchParams& P, void* proj,
 // run sums of at most a few thousand same-sign terms) to the nearest
 // integer, so every partial sum stays below 2^31 in magnitude; the rounding
 // error of an add is at most 1/(2S) ~ bound 2^-32.  A non-finite
-// projection value makes the whole footprint NaN.
+// projection value makes the whole dose NaN (the workgroups add nothing and
+// the dose copy writes NaN).
 //
 // Run aggregation keeps the 8 corner sums of consecutive samples in one cell
 // in registers and adds them to LDS when the cell changes; the sums restart
