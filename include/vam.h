@@ -280,10 +280,10 @@ vam_status vam_export_rays(vam_geometry_t h, double* out);
  *   op 5, threads:  workgroup size of the box deposit, 256 (default) or 512.
  *   op 7, order:    as op 4, for the forward projection (default 16).
  *   op 8, 9:        work order of the deposit (8) or forward (9) box
- *                   kernels: 0 = boxes fastest (forward default), 1 =
- *                   XCD-aware with all angles of a box on one XCD, A >= 2 =
- *                   XCD-aware with the angles of a box in blocks of A (up
- *                   to 4096; deposit default 8).
+ *                   kernels: 0 = boxes fastest, 1 = XCD-aware with all
+ *                   angles of a box on one XCD, A >= 2 = XCD-aware with the
+ *                   angles of a box in blocks of A (up to 4096; default 8
+ *                   for both).
  *   op 10, lanes:   lanes per segment in the default (fixed-point) box
  *                   forward: 0 = default: 2 for FP32 volumes, 1 for BF16
  *                   and FP16; 1; or 2 (two lanes take alternate samples of

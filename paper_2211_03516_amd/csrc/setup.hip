@@ -370,6 +370,7 @@ vam_status vam_setup_geometry(const vam_geometry_desc* desc, hipStream_t stream,
   h->seg_order_fwd = 16;  // ray order, then the box by length in steps of two samples (fastest measured)
   h->deposit_threads = 256;
   h->xcd_deposit = 8;  // XCD-aware deposit order, angles in blocks of 8 (fastest measured)
+  h->xcd_forward = 8;  // the same for the forward: its segment records come from the XCD's L2
   h->forward_lanes = 0;  // by volume format: 2 for FP32, 1 for 16-bit pairs (fastest measured)
   h->angles.resize(desc->n_angles);
   for (int a = 0; a < desc->n_angles; ++a)
