@@ -255,8 +255,9 @@ vam_status vam_export_rays(vam_geometry_t h, double* out);
  *   op 1, deposit:  0 = default: lab-box tiled, footprint summed in LDS in
  *                   32-bit fixed point (the scale of each box and angle
  *                   bounds every partial sum below 2^31; rounding <= 2^-31
- *                   of that bound per add; a non-finite projection value
- *                   makes its footprint NaN), then FP64 global adds;
+ *                   of that bound per add), then 64-bit integer adds into
+ *                   the voxels (deterministic; a non-finite projection
+ *                   value makes the whole dose NaN);
  *                   1 = ray-driven reference with FP64 global atomics;
  *                   2 = voxel-driven gather through an inverse ray map
  *                   (lab-frame unit cells -> sample runs; built on first
