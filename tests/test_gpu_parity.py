@@ -600,12 +600,18 @@ def test_work_orders_agree():
     y = rng.uniform(10 * 40 * 40).reshape(10, 40, 40)
     og = oracle.Geometry(p)
     Pref, Dref = oracle.forward(og, x), oracle.adjoint(og, y)
+    first = None
     for blk in (0, 1, 3, 8, 64):
         g.set_angle_blocks(deposit=blk, forward=blk)
-        ef = relL2(g.forward(to_dev(x)).cpu().numpy(), Pref)
-        ea = relL2(g.back(to_dev(y)).cpu().numpy(), Dref)
+        P, D = g.forward(to_dev(x)), g.back(to_dev(y))
+        ef = relL2(P.cpu().numpy(), Pref)
+        ea = relL2(D.cpu().numpy(), Dref)
         say("angle block %d: forward %.3e deposit %.3e" % (blk, ef, ea))
         assert ef <= 1e-5 and ea <= 1e-5
+        # integer sums per pixel and per voxel: the same bits in every order
+        if first is None:
+            first = (P, D)
+        assert torch.equal(P, first[0]) and torch.equal(D, first[1])
     g.close()
 
 
@@ -831,6 +837,20 @@ def test_c2_full_mirror_symmetry(c2_full):
     say("mirror: forward rel-L2 %.3e, deposit rel-L2 %.3e" % (ef, ed))
     assert ef <= 1e-6 and ed <= 1e-6
     gm.close()
+
+
+def test_c2_full_bitwise_repeatable(c2_full):
+    """At the full benchmark size both operators give the same bits on every
+    call (integer sums per pixel and per voxel), with FP32 and BF16 data."""
+    p, t, g = c2_full
+    rng = synth.SplitMix64(29)
+    y = torch.from_numpy(rng.uniform(360 * 256 * 256).reshape(360, 256, 256).astype(np.float32)).to(DEV)
+    say("c2 full, two calls of each operator")
+    for tdt in (torch.float32, torch.bfloat16):
+        x = to_dev(t, tdt)
+        yy = y.to(tdt)
+        assert torch.equal(g.forward(x, out_dtype=tdt), g.forward(x, out_dtype=tdt))
+        assert torch.equal(g.back(yy), g.back(yy))
 
 
 def test_c2_full_adjoint_identity(c2_full):
