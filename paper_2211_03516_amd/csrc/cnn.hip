@@ -73,11 +73,11 @@ __device__ inline void fetch_t(uint4 (&v)[2], const uint16_t* src, int64_t k0, i
 #pragma unroll
   for (int e = 0; e < 2; ++e) {
     v[e] = make_uint4(0, 0, 0, 0);
-    const int64_t p = k0 + pp + e;
+    const int p = (int)k0 + pp + e;  // pixel indices fit 31 bits (checked at creation)
     if (ok) {
-      const int x = (int)(p % W), y = (int)((p / W) % H);
+      const int x = p % W, y = (p / W) % H;
       if (y + dy >= 0 && y + dy < H && x + dx >= 0 && x + dx < W)
-        v[e] = *(const uint4*)(src + (p + dy * W + dx) * cp + c);
+        v[e] = *(const uint4*)(src + ((int64_t)p + dy * W + dx) * cp + c);
     }
   }
 }
