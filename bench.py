@@ -185,7 +185,7 @@ def main():
     ap.add_argument("--seg-order-fwd", type=int, default=-1, help="segment order of the forward")
     ap.add_argument("--deposit-threads", type=int, default=0)
     ap.add_argument("--angle-block", default="", help="deposit[,forward] angle blocks of the XCD-aware work order")
-    ap.add_argument("--forward-lanes", type=int, default=0, help="lanes per segment of the box forward (1 or 2)")
+    ap.add_argument("--forward-lanes", type=int, default=0, help="march mode of the box forward (1: one lane, 2: two lanes, 3: cached cell)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")

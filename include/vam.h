@@ -285,12 +285,14 @@ vam_status vam_export_rays(vam_geometry_t h, double* out);
  *                   angles of a box on one XCD, A >= 2 = XCD-aware with the
  *                   angles of a box in blocks of A (up to 4096; default 8
  *                   for both).
- *   op 10, lanes:   lanes per segment in the default (fixed-point) box
- *                   forward: 0 = default: 2 for FP32 volumes, 1 for BF16
- *                   and FP16; 1; or 2 (two lanes take alternate samples of
- *                   a segment, each summing with r^2; their samples are
- *                   half a voxel apart, so they often read the same LDS
- *                   words).
+ *   op 10, mode:    how the default (fixed-point) box forward marches a
+ *                   segment: 1 = one lane; 2 = two lanes take alternate
+ *                   samples, each summing with r^2 (their samples are half
+ *                   a voxel apart, so they often read the same LDS words);
+ *                   3 = one lane that keeps the current cell's LDS words in
+ *                   registers and reads LDS only when its cell changes
+ *                   (the same bits as 1); 0 = default: 3 for FP32 and BF16
+ *                   volumes, 1 for FP16.
  * A failed rebuild (ops 2, 4, 7) leaves the handle without a box
  * decomposition: the box kernels then return VAM_ERR_INVALID_ARG until a
  * rebuild succeeds.  Errors: VAM_ERR_BAD_HANDLE, VAM_ERR_INVALID_ARG for an

@@ -264,8 +264,10 @@ class Geometry:
         _check(lib().vam_set_variant(self.handle, OP_SEG_ORDER_FWD if forward else OP_SEG_ORDER, int(order)))
 
     def set_forward_lanes(self, lanes):
-        """Lanes per segment in the fixed-point box forward: 1, 2, or 0 (the
-        default: 2 for FP32 volumes, 1 for BF16/FP16)."""
+        """March mode of the fixed-point box forward: 1 (one lane per
+        segment), 2 (two lanes, alternate samples), 3 (one lane keeping the
+        cell's LDS words in registers; the same bits as 1) or 0 (the default:
+        3 for FP32/BF16 volumes, 1 for FP16)."""
         _check(lib().vam_set_variant(self.handle, OP_FORWARD_LANES, int(lanes)))
 
     def set_angle_blocks(self, deposit=None, forward=None):

@@ -688,6 +688,62 @@ __device__ inline float march_forward(const uint32_t* sv, const SegPos& g, float
   return S;
 }
 
+// The same sum, one lane per segment, keeping the LDS words of the current
+// cell in registers: a sample in the same cell as the one before reads no
+// LDS (the reads are issued only for lanes whose cell changed).
+template <int SY, int SZ, bool CLAMP, int FMT>
+__device__ inline float march_forward_cached(const uint32_t* sv, const SegPos& g, float hx, float hy, float hz,
+                                             float r_hi, float r_lo) {
+  constexpr bool F32 = FMT == kVolF32;
+  float S = 0.0f;
+  unsigned cur = 0xffffffffu;
+  uint32_t w[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (float kf = g.k1; kf >= g.k0; kf -= 1.0f) {
+    const float x = coord<CLAMP>(kf, g.dx, g.px, hx);
+    const float y = coord<CLAMP>(kf, g.dy, g.py, hy);
+    const float z = coord<CLAMP>(kf, g.dz, g.pz, hz);
+    const float fx = __builtin_amdgcn_fractf(x), fy = __builtin_amdgcn_fractf(y), fz = __builtin_amdgcn_fractf(z);
+    const unsigned o = __umul24((unsigned)z, SZ) + __umul24((unsigned)y, SY) + (unsigned)x;
+    if (o != cur) {
+      cur = o;
+      w[0] = sv[o];
+      w[2] = sv[o + SY];
+      w[4] = sv[o + SZ];
+      w[6] = sv[o + SZ + SY];
+      if constexpr (F32) {
+        w[1] = sv[o + 1];
+        w[3] = sv[o + SY + 1];
+        w[5] = sv[o + SZ + 1];
+        w[7] = sv[o + SZ + SY + 1];
+      }
+    }
+    float c[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if constexpr (F32) {
+        const float lo = __uint_as_float(w[2 * j]), hi = __uint_as_float(w[2 * j + 1]);
+        c[j] = fmaf(fx, hi - lo, lo);
+      } else if constexpr (FMT == kVolBF16Pairs) {
+        const float lo = __uint_as_float(w[2 * j] << 16), hi = __uint_as_float(w[2 * j] & 0xffff0000u);
+        c[j] = fmaf(fx, hi - lo, lo);
+      } else {
+        float d;
+        asm("v_fma_mix_f32 %0, %1, 1.0, -%1 op_sel:[1,0,0] op_sel_hi:[1,0,1]" : "=v"(d) : "v"(w[2 * j]));
+        const float lo = (float)__builtin_bit_cast(_Float16, (unsigned short)(w[2 * j] & 0xffffu));
+        c[j] = fmaf(fx, d, lo);
+      }
+    }
+    const float c0 = fmaf(fy, c[1] - c[0], c[0]);
+    const float c1 = fmaf(fy, c[3] - c[2], c[2]);
+    const float val = fmaf(fz, c1 - c0, c0);
+    S = fmaf(S, r_hi, fmaf(S, r_lo, val));
+  }
+  return S;
+}
+
+// March modes of the fixed-point box forward (k_forward_box's MODE).
+constexpr int kMarchOne = 1, kMarchPair = 2, kMarchCached = 3;
+
 // Fixed-point forward (the default).  A pixel's value is a sum of segment
 // partials pw.w S, each at most (step / n_pupil) n V in magnitude (sample
 // weights <= step / n_pupil, attenuation <= 1, trilinear values <= V, the
@@ -702,11 +758,13 @@ __device__ inline float march_forward(const uint32_t* sv, const SegPos& g, float
 // vol: the padded working volume, FP32 values or 16-bit pairs (FMT).
 // FX = false: partial sums to part[angle][rank][ray] (slots per angle);
 // FX = true: fixed-point adds into pfx[angle][pixel].
-// LP = 2: two neighbouring lanes share a segment, one taking its even and
-// the other its odd samples (Horner with r^2 each; the pair's sum is
-// S_even + r S_odd).  Their samples are half a voxel apart, so they often
+// MODE: how lanes march a segment.  kMarchOne: one lane, all samples.
+// kMarchPair: two neighbouring lanes share a segment, one taking its even
+// and the other its odd samples (Horner with r^2 each; the pair's sum is
+// S_even + r S_odd); their samples are half a voxel apart, so they often
 // read the same LDS words, which the LDS serves as one broadcast.
-template <int B, int FMT, bool FX, int LP>
+// kMarchCached: one lane, the current cell's LDS words kept in registers.
+template <int B, int FMT, bool FX, int MODE>
 __global__ __launch_bounds__(256) void k_forward_box(MarchParams P, BoxParams Bp, const uint32_t* __restrict__ vol,
                                                      float* __restrict__ part, int64_t slots,
                                                      unsigned long long* __restrict__ pfx,
@@ -737,12 +795,16 @@ __global__ __launch_bounds__(256) void k_forward_box(MarchParams P, BoxParams Bp
     scale = fx_scale(vm, fx_coef);
   }
   unsigned long long* row = pfx + (int64_t)a * Bp.npix;
-  const int part_of = LP == 2 ? (int)(threadIdx.x & 1u) : 0;
-  for (int si = Bp.box_begin[b] + (int)threadIdx.x / LP; si < s_end; si += (int)blockDim.x / LP) {
+  const int part_of = MODE == kMarchPair ? (int)(threadIdx.x & 1u) : 0;
+  constexpr int LPS = MODE == kMarchPair ? 2 : 1;  // lanes per segment
+  for (int si = Bp.box_begin[b] + (int)threadIdx.x / LPS; si < s_end; si += (int)blockDim.x / LPS) {
     const float4 pw = Bp.seg.pw[si], dn = Bp.seg.dn[si];
     const SegPos g = seg_pos(pw, dn, __float_as_int(dn.w), f, c, s, sc, ss, P.step);
     float S;
-    if constexpr (LP == 1) {
+    if constexpr (MODE == kMarchCached) {
+      S = seg_inside(g, hx, hy, hz) ? march_forward_cached<SY, SZ, false, FMT>(sv, g, hx, hy, hz, P.r_hi, P.r_lo)
+                                    : march_forward_cached<SY, SZ, true, FMT>(sv, g, hx, hy, hz, P.r_hi, P.r_lo);
+    } else if constexpr (MODE == kMarchOne) {
       S = seg_inside(g, hx, hy, hz)
               ? march_forward<SY, SZ, false, FMT, 1>(sv, g, g.k0, g.k1, hx, hy, hz, P.r_hi, P.r_lo)
               : march_forward<SY, SZ, true, FMT, 1>(sv, g, g.k0, g.k1, hx, hy, hz, P.r_hi, P.r_lo);
@@ -873,18 +935,21 @@ struct FwdOut {
   unsigned long long* pfx;  // fixed-point projections (fx = true)
   const unsigned* vmax;
   double fx_coef;
-  int lanes;                // lanes per segment (fx = true): 1 or 2
+  int mode;                 // march mode (fx = true): kMarchOne, kMarchPair or kMarchCached
 };
 
 template <int B, int FMT, bool FX>
 static void launch_forward_box_f(dim3 grid, hipStream_t s, const MarchParams& P, const BoxParams& Bp,
                                  const uint32_t* vol, const FwdOut& o) {
-  if (FX && o.lanes == 2)
-    hipLaunchKernelGGL((k_forward_box<B, FMT, true, 2>), grid, dim3(256), 0, s, P, Bp, vol, o.part, o.slots, o.pfx,
-                       o.vmax, o.fx_coef);
+  if (FX && o.mode == kMarchCached)
+    hipLaunchKernelGGL((k_forward_box<B, FMT, true, kMarchCached>), grid, dim3(256), 0, s, P, Bp, vol, o.part,
+                       o.slots, o.pfx, o.vmax, o.fx_coef);
+  else if (FX && o.mode == kMarchPair)
+    hipLaunchKernelGGL((k_forward_box<B, FMT, true, kMarchPair>), grid, dim3(256), 0, s, P, Bp, vol, o.part, o.slots,
+                       o.pfx, o.vmax, o.fx_coef);
   else
-    hipLaunchKernelGGL((k_forward_box<B, FMT, FX, 1>), grid, dim3(256), 0, s, P, Bp, vol, o.part, o.slots, o.pfx,
-                       o.vmax, o.fx_coef);
+    hipLaunchKernelGGL((k_forward_box<B, FMT, FX, kMarchOne>), grid, dim3(256), 0, s, P, Bp, vol, o.part, o.slots,
+                       o.pfx, o.vmax, o.fx_coef);
 }
 
 template <int B, bool FX>
@@ -956,11 +1021,11 @@ static vam_status forward_box_fx(vam_geometry* h, const MarchParams& P, PT* proj
   const double coef = D.step / D.n_pupil * (double)h->pix_samples_max;
   if (h->n_boxes > 0) {
     const BoxParams Bp = box_params(h, h->seg_fwd, na, h->xcd_forward);
-    // two lanes per segment halve the FP32 loop's LDS bank conflicts (it is
-    // bound by its LDS reads); the 16-bit pair loops are bound by VALU issue,
-    // which the pairing's per-segment work only adds to
-    const int lanes = h->forward_lanes ? h->forward_lanes : (fmt == kVolF32 ? 2 : 1);
-    const FwdOut o{nullptr, 0, pfx, h->vol_absmax, coef, lanes};
+    // the loops are bound by their LDS reads (FP32) or VALU issue (16-bit
+    // pairs); keeping the cell's words in registers saves LDS reads for FP32
+    // and BF16, while FP16's mixed-precision FMA reads its word directly
+    const int mode = h->forward_lanes ? h->forward_lanes : (fmt == kVolF16Pairs ? kMarchOne : kMarchCached);
+    const FwdOut o{nullptr, 0, pfx, h->vol_absmax, coef, mode};
     launch_forward_box_edge<true>(h->boxes.B, work_grid(h->n_boxes, na, Bp.xcd), s, P, Bp, fmt, vol, o);
   }
   hipLaunchKernelGGL(k_fx_store<PT>, dim3((unsigned)std::max<int64_t>((n + 255) / 256, 1)), dim3(256), 0, s, pfx,
@@ -996,7 +1061,7 @@ static vam_status forward_box_t(vam_geometry* h, const MarchParams& P0, PT* proj
     P.a0 = P0.a0 + c0;
     if (h->n_boxes > 0) {
       const BoxParams Bp = box_params(h, h->seg_fwd, nc, h->xcd_forward);
-      const FwdOut o{h->seg_part, slots, nullptr, nullptr, 0.0, 1};
+      const FwdOut o{h->seg_part, slots, nullptr, nullptr, 0.0, kMarchOne};
       launch_forward_box_edge<false>(h->boxes.B, work_grid(h->n_boxes, nc, Bp.xcd), s, P, Bp, fmt,
                                      (const uint32_t*)h->vol_pad, o);
     }

@@ -371,7 +371,7 @@ vam_status vam_setup_geometry(const vam_geometry_desc* desc, hipStream_t stream,
   h->deposit_threads = 256;
   h->xcd_deposit = 8;  // XCD-aware deposit order, angles in blocks of 8 (fastest measured)
   h->xcd_forward = 8;  // the same for the forward: its segment records come from the XCD's L2
-  h->forward_lanes = 0;  // by volume format: 2 for FP32, 1 for 16-bit pairs (fastest measured)
+  h->forward_lanes = 0;  // by volume format: cached cell words for FP32 and BF16, one lane for FP16 (fastest measured)
   h->angles.resize(desc->n_angles);
   for (int a = 0; a < desc->n_angles; ++a)
     h->angles[a] = desc->angles_rad ? desc->angles_rad[a] : 2.0 * M_PI * a / desc->n_angles;
@@ -511,7 +511,7 @@ vam_status vam_set_variant(vam_geometry_t h, int32_t op, int32_t variant) {
     if (variant < 0 || variant > 4096) return fail(VAM_ERR_INVALID_ARG, "angle block must be in [0, 4096]");
     (op == 8 ? h->xcd_deposit : h->xcd_forward) = variant;
   } else if (op == 10) {
-    if (variant < 0 || variant > 2) return fail(VAM_ERR_INVALID_ARG, "lanes per segment must be 0, 1 or 2");
+    if (variant < 0 || variant > 3) return fail(VAM_ERR_INVALID_ARG, "forward march mode must be 0, 1, 2 or 3");
     h->forward_lanes = variant;
   } else {
     return fail(VAM_ERR_INVALID_ARG, "unknown operator %d", op);

@@ -402,12 +402,14 @@ def test_fixed_point_forward():
     Ph = g.forward(to_dev(hdr)).cpu().numpy().astype(np.float64)
     g.set_forward_lanes(1)  # the same per-segment sums as variant 2
     Ph1 = g.forward(to_dev(hdr)).cpu().numpy().astype(np.float64)
+    g.set_forward_lanes(2)
+    Ph2 = g.forward(to_dev(hdr)).cpu().numpy().astype(np.float64)
     g.set_forward_lanes(0)
     g.set_forward_variant(vam.FWD_PARTIALS)
     Pp = g.forward(to_dev(hdr)).cpu().numpy().astype(np.float64)
     g.set_forward_variant(vam.FWD_DEFAULT)
     sel = np.abs(Pp) >= 1e-9 * np.abs(Pp).max()
-    for what, Px in (("one lane", Ph1), ("two lanes", Ph)):
+    for what, Px in (("one lane", Ph1), ("two lanes", Ph2), ("default", Ph)):
         rel = np.abs(Px - Pp)[sel] / np.abs(Pp)[sel]
         say("fixed-point forward (%s), 1e8 block in U(0, 1): %d of %d pixels, max relative difference to "
             "FP32 partial sums %.2e" % (what, sel.sum(), sel.size, rel.max()))
@@ -422,11 +424,12 @@ def test_fixed_point_forward():
 
 
 def test_forward_lanes_per_segment():
-    """The fixed-point forward with two lanes per segment (alternate samples,
-    each lane's Horner sum over r^2, combined as S_even + r S_odd) and with
-    one, against the oracle: signed FP32, BF16 and FP16 volumes,
-    every box edge, and a strongly absorbing resin (r far from 1), where a
-    wrong power of r on any part would show."""
+    """The fixed-point forward's march modes against the oracle: two lanes
+    per segment (alternate samples, each lane's Horner sum over r^2, combined
+    as S_even + r S_odd), one lane, and one lane keeping its cell's LDS words
+    (the same bits as one lane); signed FP32, BF16 and FP16 volumes, every
+    box edge, and a strongly absorbing resin (r far from 1), where a wrong
+    power of r on any part would show."""
     n = 40
     for alpha in (0.02, 0.6):
         p = c2_small(n, n_pupil=4, n_angles=5, alpha=alpha)
@@ -435,7 +438,8 @@ def test_forward_lanes_per_segment():
         rng = synth.SplitMix64(29)
         x = rng.uniform(n ** 3).reshape(n, n, n) - 0.3
         ref = oracle.forward(og, x)
-        for lanes in (1, 2):
+        one = {}
+        for lanes in (1, 2, 3):
             g.set_forward_lanes(lanes)
             for edge in (8, 16, 12):
                 g.set_box_edge(edge)
@@ -443,15 +447,27 @@ def test_forward_lanes_per_segment():
                       what="%d lanes, alpha %g, edge %d" % (lanes, alpha, edge))
             P1 = g.forward(to_dev(x))
             assert torch.equal(P1, g.forward(to_dev(x)))
+            outs = {"f32": P1}
             for dt, tdt in (("bf16", torch.bfloat16), ("f16", torch.float16)):
                 xs = torch.from_numpy(x).to(tdt)
-                check(g.forward(xs.to(DEV)).cpu().numpy(), oracle.forward(og, xs.double().numpy()),
+                outs[dt] = g.forward(xs.to(DEV))
+                check(outs[dt].cpu().numpy(), oracle.forward(og, xs.double().numpy()),
                       what="%d lanes, alpha %g, %s pairs" % (lanes, alpha, dt))
+            if lanes == 1:
+                one = outs
+            elif lanes == 3:
+                # the cached cell words change where the values are read
+                # from, not the arithmetic
+                for dt in outs:
+                    assert torch.equal(outs[dt], one[dt]), dt
         with pytest.raises(vam.VamError):
             g.set_forward_lanes(4)
-        # the default picks by format (two lanes for FP32): the same bits
+        # the default picks by format (cached cell words for FP32, one lane
+        # for FP16): the same bits as one lane
         g.set_forward_lanes(0)
-        assert torch.equal(g.forward(to_dev(x)), P1)
+        assert torch.equal(g.forward(to_dev(x)), one["f32"])
+        xs = torch.from_numpy(x).to(torch.float16).to(DEV)
+        assert torch.equal(g.forward(xs), one["f16"])
         g.close()
 
 
