@@ -284,7 +284,7 @@ vam_status vam_export_rays(vam_geometry_t h, double* out);
  *                   kernels: 0 = boxes fastest, 1 = XCD-aware with all
  *                   angles of a box on one XCD, A >= 2 = XCD-aware with the
  *                   angles of a box in blocks of A (up to 4096; default 8
- *                   for both).
+ *                   for the deposit, 16 for the forward).
  *   op 10, mode:    how the default (fixed-point) box forward marches a
  *                   segment: 1 = one lane; 2 = two lanes take alternate
  *                   samples, each summing with r^2 (their samples are half

@@ -370,7 +370,7 @@ vam_status vam_setup_geometry(const vam_geometry_desc* desc, hipStream_t stream,
   h->seg_order_fwd = 16;  // ray order, then the box by length in steps of two samples (fastest measured)
   h->deposit_threads = 256;
   h->xcd_deposit = 8;  // XCD-aware deposit order, angles in blocks of 8 (fastest measured)
-  h->xcd_forward = 8;  // the same for the forward: its segment records come from the XCD's L2
+  h->xcd_forward = 16;  // the same for the forward, in blocks of 16: its segment records come from the XCD's L2
   h->forward_lanes = 0;  // by volume format: cached cell words for FP32 and BF16, one lane for FP16 (fastest measured)
   h->angles.resize(desc->n_angles);
   for (int a = 0; a < desc->n_angles; ++a)
