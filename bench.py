@@ -132,17 +132,19 @@ def learned_vs_plain():
 
 
 def cpu_baseline(p, target, threads):
-    """The FP64 oracle on a bounded sample of the same workload."""
-    import numpy as np
+    """The FP64 oracle on a bounded sample of the same workload: the forward
+    and the dose deposit of 8 evenly spaced angles (every angle of the turn
+    holds the same samples, by the rotational symmetry about z, so the full
+    pass is these 8 scaled by n_angles / 8)."""
     import oracle
     og = oracle.Geometry(p)
-    angles = [0, p["n_angles"] // 2]
+    n_ang = p["n_angles"]
+    angles = sorted({k * n_ang // 8 for k in range(8)})
     n_samples = 0
     t0 = time.perf_counter()
-    P = oracle.forward(og, target, a0=angles[0], na=1, nthreads=threads)
-    P2 = oracle.forward(og, target, a0=angles[1], na=1, nthreads=threads)
-    oracle.adjoint(og, P, a0=angles[0], na=1, nthreads=threads)
-    oracle.adjoint(og, P2, a0=angles[1], na=1, nthreads=threads)
+    for a in angles:
+        P = oracle.forward(og, target, a0=a, na=1, nthreads=threads)
+        oracle.adjoint(og, P, a0=a, na=1, nthreads=threads)
     dt = time.perf_counter() - t0
     for a in angles:
         n_samples += 2 * oracle.count_samples(og, a0=a, na=1, nthreads=threads)
@@ -161,8 +163,9 @@ def cpu_baseline(p, target, threads):
         pass
     return {
         "value": n_samples / dt, "unit": "samples/s", "cores": threads, "kind": "oracle",
-        "sample": "forward + dose deposit of angles %d and %d of the same workload " % tuple(angles) +
+        "sample": "forward + dose deposit of angles %s of the same workload " % ", ".join(map(str, angles)) +
                   "(%d samples, %.1f s wall, FP64 C++ std::thread)" % (n_samples, dt),
+        "full_pass_s_extrapolated": dt * n_ang / len(angles),
         "single_thread": {"value": n1 / dt1, "unit": "samples/s",
                           "sample": "forward of angle %d on one thread (%d samples, %.1f s)" % (angles[0], n1, dt1)},
         "host": {"cpu_model": model, "logical_cpus": os.cpu_count()},
@@ -175,8 +178,8 @@ def main():
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOAD_NAMES))
     ap.add_argument("--dtype", default="f32", choices=["f32", "bf16", "f16"],
                     help="storage type of the volume and projections (accumulation is FP32/FP64)")
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--adjoint-variant", type=int, default=0)
     ap.add_argument("--forward-variant", type=int, default=0)
@@ -321,6 +324,7 @@ def main():
                    "forward_variant": args.forward_variant, "box_edge": args.box_edge},
         "roofline": roofline,
         "kernels_ms": {"forward": f_avg, "deposit": b_avg,
+                       "forward_median": float(np.median(fwd_ms)), "deposit_median": float(np.median(back_ms)),
                        "deposit_sparse_ms": float(np.mean(sparse_ms)) if sparse_ms else None,
                        "sparse_nonzero_pixel_fraction": active},
         "gather_model": {"bytes_per_sample": GATHER_BYTES_PER_SAMPLE, "kernel": dom,
