@@ -143,7 +143,7 @@ struct vam_geometry {
   int64_t samples_per_pass;
   int32_t adjoint_variant;
   int32_t forward_variant;
-  int32_t forward_lanes;          // lanes per segment in the fixed-point box forward: 1, 2, or 0 (by format)
+  int32_t forward_lanes;          // march mode of the fixed-point box forward: 1, 2, 3, or 0 (by format)
 };
 
 namespace vam {
