@@ -462,12 +462,13 @@ def test_forward_lanes_per_segment():
                     assert torch.equal(outs[dt], one[dt]), dt
         with pytest.raises(vam.VamError):
             g.set_forward_lanes(4)
-        # the default picks by format (cached cell words for FP32, one lane
-        # for FP16): the same bits as one lane
+        # the default picks by format (cached cell words for FP32 and BF16,
+        # one lane for FP16): the same bits as one lane
         g.set_forward_lanes(0)
         assert torch.equal(g.forward(to_dev(x)), one["f32"])
-        xs = torch.from_numpy(x).to(torch.float16).to(DEV)
-        assert torch.equal(g.forward(xs), one["f16"])
+        for dt, tdt in (("bf16", torch.bfloat16), ("f16", torch.float16)):
+            xs = torch.from_numpy(x).to(tdt).to(DEV)
+            assert torch.equal(g.forward(xs), one[dt]), dt
         g.close()
 
 
