@@ -1,6 +1,7 @@
 """Host-side parts of the benchmark contract: the multi-GPU refusal, the
-secondary metric read from the committed learned-initialiser run and the
-traffic figure's guard on the kernel sources."""
+secondary metric read from the committed learned-initialiser run, the
+traffic figure's guard on the kernel sources and the oracle baseline's
+sample of the workload."""
 import json
 import os
 import subprocess
@@ -58,3 +59,21 @@ def test_roofline_flop_count_matches_its_breakdown():
     fwd = 6 + 3 + 7 * 3 + 2
     dep = 6 + 3 + 6 + 8 + 8 + 1
     assert bench.FLOP_PER_SAMPLE == {"forward": fwd, "deposit": dep}
+
+
+def test_cpu_baseline_times_eight_evenly_spaced_angles():
+    import oracle
+    import synth
+    p = synth.workload("c1")
+    target, _ = synth.random_config1_target(p["nx"], p["r_inner"], seed=0)
+    d = bench.cpu_baseline(p, target, 2)
+    assert d["kind"] == "oracle" and d["cores"] == 2 and d["unit"] == "samples/s" and d["value"] > 0
+    n = p["n_angles"]
+    angles = [k * n // 8 for k in range(8)]
+    assert d["sample"].startswith("forward + dose deposit of angles %s " % ", ".join(map(str, angles)))
+    # forward and deposit of each of the 8 angles; every angle holds the
+    # same samples (the resin lies inside the grid's inscribed cylinder)
+    per_angle = oracle.count_samples(oracle.Geometry(p), a0=0, na=1, nthreads=2)
+    assert "(%d samples" % (2 * 8 * per_angle) in d["sample"]
+    assert d["full_pass_s_extrapolated"] > 0
+    assert d["single_thread"]["value"] > 0 and "(%d samples" % per_angle in d["single_thread"]["sample"]
